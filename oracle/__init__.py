@@ -1,0 +1,383 @@
+"""FaSS-MVS CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Plain single-threaded reference of the method's hot path, used by the tests,
+the smoke check and the benchmark's CPU-baseline leg only.  The per-pixel
+stages live in ``fassmvs_oracle.cpp`` (built to ``liboracle.so``); this
+module binds them with ctypes and drives one frame coarse-to-fine
+(pipeline overview of the paper's methodology section).  It shares no code
+with the GPU library.
+
+Parity status: pinned by the CPU tests (closed forms, brute force,
+invariants, ground-truth recovery); normal smoothing and confidence are
+pinned only on their closed-form special cases ("parity unpinned" beyond
+those, tolerance derived from float arithmetic).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fassmvs_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+DIRS = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (no fused multiply-add, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-fno-fast-math", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = C.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _declare(L):
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    sig = {
+        "or_kinv_level": (i, [vp, i, vp, vp]),
+        "or_relative_pose": (None, [vp, vp, vp, vp, vp, vp]),
+        "or_homography": (None, [vp, vp, vp, vp, vp, d, vp]),
+        "or_plane_list": (None, [d, d, i, vp]),
+        "or_depth_on_plane": (d, [vp, vp, d, i, i]),
+        "or_p2_lut": (None, [i, i, i, d, d, vp]),
+        "or_pyr_down": (i, [vp, i, i, vp]),
+        "or_warp": (None, [vp, i, i, vp, i, i, vp]),
+        "or_census": (i, [vp, i, i, i, i, vp]),
+        "or_census_u8": (i, [vp, i, i, i, i, vp]),
+        "or_cost_volume": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, vp, vp, vp]),
+        "or_cost_sample": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, i, i, i, i]),
+        "or_sgm": (i, [i, i, i, vp, vp, vp, vp, i, vp, vp, i, vp, vp]),
+        "or_wta_refine": (None, [i, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "or_median5": (None, [vp, i, i, vp]),
+        "or_normals": (None, [vp, i, i, vp, vp]),
+        "or_normal_smooth": (None, [vp, vp, i, i, i, d, vp]),
+        "or_confidence": (None, [vp, vp, vp, vp, i, i, d, vp]),
+        "or_upsample_nn": (None, [vp, i, i, i, i, i, vp]),
+        "or_window_offsets": (None, [vp, i, i, vp, i, vp, vp, vp, vp, vp, vp]),
+        "or_delta_i": (None, [vp, vp, i, i, vp, i, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers
+# ---------------------------------------------------------------------------
+
+def kinv_level(K, level):
+    K = _c(K, np.float64)
+    Ki = np.zeros(9)
+    Kl = np.zeros(9)
+    if lib().or_kinv_level(_p(K), level, _p(Ki), _p(Kl)) != 0:
+        raise ValueError("intrinsics must be upper triangular with K[2,2] = 1")
+    return Ki.reshape(3, 3), Kl.reshape(3, 3)
+
+
+def relative_pose(Rref, tref, Rk, tk):
+    R = np.zeros(9)
+    t = np.zeros(3)
+    lib().or_relative_pose(_p(_c(Rref, np.float64)), _p(_c(tref, np.float64)),
+                           _p(_c(Rk, np.float64)), _p(_c(tk, np.float64)), _p(R), _p(t))
+    return R.reshape(3, 3), t
+
+
+def homography(Kl, Kinv, R, t, n, delta):
+    H = np.zeros(9)
+    lib().or_homography(_p(_c(Kl, np.float64)), _p(_c(Kinv, np.float64)), _p(_c(R, np.float64)),
+                        _p(_c(t, np.float64)), _p(_c(n, np.float64)), float(delta), _p(H))
+    return H.reshape(3, 3)
+
+
+def plane_list(dmin, dmax, G):
+    out = np.zeros(G)
+    lib().or_plane_list(float(dmin), float(dmax), int(G), _p(out))
+    return out
+
+
+def depth_on_plane(Kinv, n, delta, x, y):
+    return lib().or_depth_on_plane(_p(_c(Kinv, np.float64)), _p(_c(n, np.float64)), float(delta), int(x), int(y))
+
+
+def p2_lut(p1, mode, p2_fixed, alpha, beta):
+    lut = np.zeros(256, np.int32)
+    lib().or_p2_lut(int(p1), int(mode), int(p2_fixed), float(alpha), float(beta), _p(lut))
+    return lut
+
+
+def pyr_down(img):
+    img = _c(img, np.uint8)
+    h, w = img.shape
+    out = np.zeros((h // 2, w // 2), np.uint8)
+    if lib().or_pyr_down(_p(img), w, h, _p(out)) != 0:
+        raise ValueError("image too small to downsample")
+    return out
+
+
+def warp(src, H, rw, rh):
+    src = _c(src, np.uint8)
+    out = np.zeros((rh, rw), np.float32)
+    lib().or_warp(_p(src), src.shape[1], src.shape[0], _p(_c(H, np.float64)), rw, rh, _p(out))
+    return out
+
+
+def census(img, cw, ch):
+    h, w = img.shape
+    out = np.zeros((h, w), np.uint64)
+    if img.dtype == np.uint8:
+        r = lib().or_census_u8(_p(_c(img, np.uint8)), w, h, cw, ch, _p(out))
+    else:
+        r = lib().or_census(_p(_c(img, np.float32)), w, h, cw, ch, _p(out))
+    if r != 0:
+        raise ValueError("census window must be odd and at most 65 pixels")
+    return out
+
+
+def _view_ptrs(views):
+    arrs = [_c(v, np.uint8) for v in views]
+    ptrs = (C.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+    return arrs, ptrs
+
+
+def cost_volume(ct_ref, views, side, cw, ch, G, W, H, offs=None):
+    """S[h][w][sum W] uint8; H: [n_views][sum G][3][3]."""
+    h, w = ct_ref.shape
+    G = np.asarray(G, np.int32)
+    W = np.asarray(W, np.int32)
+    arrs, ptrs = _view_ptrs(views)
+    side = _c(side, np.int8)
+    H = _c(H, np.float64)
+    S = np.zeros((h, w, int(W.sum())), np.uint8)
+    offs_c = _c(offs, np.int32) if offs is not None else None
+    r = lib().or_cost_volume(w, h, _p(_c(ct_ref, np.uint64)), len(arrs), C.cast(ptrs, C.c_void_p), _p(side),
+                             cw, ch, len(G), _p(G), _p(W), _p(H), _p(offs_c), _p(S))
+    if r != 0:
+        raise ValueError("cost volume: bad arguments or 8-bit overflow (%d)" % r)
+    return S
+
+
+def cost_sample(ct_ref, views, side, cw, ch, G, H, f, g, x, y):
+    h, w = ct_ref.shape
+    G = np.asarray(G, np.int32)
+    arrs, ptrs = _view_ptrs(views)
+    return lib().or_cost_sample(w, h, _p(_c(ct_ref, np.uint64)), len(arrs), C.cast(ptrs, C.c_void_p),
+                                _p(_c(side, np.int8)), cw, ch, len(G), _p(G), _p(_c(H, np.float64)),
+                                int(f), int(g), int(x), int(y))
+
+
+def sgm(S, W, p1, lut, ref, n_paths, offs=None, dI=None, want_sbar=True, want_lr=False):
+    h, w, D = S.shape
+    W = np.asarray(W, np.int32)
+    Sbar = np.zeros((h, w, D), np.uint16) if want_sbar else None
+    Lr = np.zeros((n_paths, h, w, D), np.uint16) if want_lr else None
+    r = lib().or_sgm(w, h, len(W), _p(W), _p(_c(offs, np.int32) if offs is not None else None),
+                     _p(_c(S, np.uint8)), _p(_c(dI, np.int8) if dI is not None else None), int(p1),
+                     _p(_c(lut, np.int32)), _p(_c(ref, np.uint8)), int(n_paths), _p(Sbar), _p(Lr))
+    if r != 0:
+        raise OverflowError("aggregated cost exceeds 16 bits")
+    return Sbar, Lr
+
+
+def wta_refine(Sbar, W, G, fam_n, fam_delta, Kinv, offs=None):
+    h, w, D = Sbar.shape
+    W = np.asarray(W, np.int32)
+    G = np.asarray(G, np.int32)
+    label = np.zeros((h, w), np.int32)
+    fam = np.zeros((h, w), np.int32)
+    depth = np.zeros((h, w), np.float32)
+    lib().or_wta_refine(w, h, len(W), _p(W), _p(G), _p(_c(offs, np.int32) if offs is not None else None),
+                        _p(_c(Sbar, np.uint16)), _p(_c(fam_n, np.float64)), _p(_c(fam_delta, np.float64)),
+                        _p(_c(Kinv, np.float64)), _p(label), _p(fam), _p(depth))
+    return label, fam, depth
+
+
+def median5(d):
+    d = _c(d, np.float32)
+    out = np.zeros_like(d)
+    lib().or_median5(_p(d), d.shape[1], d.shape[0], _p(out))
+    return out
+
+
+def normals(depth, Kinv):
+    depth = _c(depth, np.float32)
+    h, w = depth.shape
+    out = np.zeros((h, w, 3), np.float32)
+    lib().or_normals(_p(depth), w, h, _p(_c(Kinv, np.float64)), _p(out))
+    return out
+
+
+def normal_smooth(n, img, radius, beta):
+    n = _c(n, np.float32)
+    h, w, _ = n.shape
+    out = np.zeros_like(n)
+    lib().or_normal_smooth(_p(n), _p(_c(img, np.uint8)), w, h, int(radius), float(beta), _p(out))
+    return out
+
+
+def confidence(n, label, fam, fam_n, rho_deg):
+    n = _c(n, np.float32)
+    h, w, _ = n.shape
+    out = np.zeros((h, w), np.float32)
+    lib().or_confidence(_p(n), _p(_c(label, np.int32)), _p(_c(fam, np.int32)), _p(_c(fam_n, np.float64)),
+                        w, h, float(rho_deg), _p(out))
+    return out
+
+
+def upsample_nn(src, dw, dh):
+    src = _c(src, np.float32)
+    sh, sw = src.shape[:2]
+    ch = 1 if src.ndim == 2 else src.shape[2]
+    out = np.zeros((dh, dw) + (() if src.ndim == 2 else (ch,)), np.float32)
+    lib().or_upsample_nn(_p(src), sw, sh, ch, dw, dh, _p(out))
+    return out
+
+
+def window_offsets(dbar, Kinv, fam_n, inv_dmin, step, G, W):
+    dbar = _c(dbar, np.float32)
+    h, w = dbar.shape
+    nf = len(G)
+    offs = np.zeros((nf, h, w), np.int32)
+    lib().or_window_offsets(_p(dbar), w, h, _p(_c(Kinv, np.float64)), nf, _p(_c(fam_n, np.float64)),
+                            _p(_c(inv_dmin, np.float64)), _p(_c(step, np.float64)),
+                            _p(np.asarray(G, np.int32)), _p(np.asarray(W, np.int32)), _p(offs))
+    return offs
+
+
+def delta_i(dbar, nbar, Kinv, fam_n, step):
+    dbar = _c(dbar, np.float32)
+    h, w = dbar.shape
+    nf = len(step)
+    out = np.zeros((8, h, w, nf), np.int8)
+    lib().or_delta_i(_p(dbar), _p(_c(nbar, np.float32)), w, h, _p(_c(Kinv, np.float64)), nf,
+                     _p(_c(fam_n, np.float64)), _p(_c(step, np.float64)), _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# frame driver
+# ---------------------------------------------------------------------------
+
+def level_plan(wl, level):
+    """Per-level plane families: plane count, window size, lists, normals."""
+    p = wl["params"]
+    n = p["n_levels"]
+    fams = wl["families"]
+    G = [int(f["count"]) << (n - 1 - level) for f in fams]
+    if level == n - 1 or p["window_labels"] <= 0:
+        W = list(G)
+    else:
+        W = [min(int(p["window_labels"]), g) for g in G]
+    deltas = [plane_list(f["delta_min"], f["delta_max"], g) for f, g in zip(fams, G)]
+    fam_n = np.array([f["n"] for f in fams], np.float64)
+    inv_dmin = np.array([1.0 / f["delta_min"] for f in fams])
+    step = np.array([(1.0 / f["delta_min"] - 1.0 / f["delta_max"]) / (g - 1) if g > 1 else 1.0
+                     for f, g in zip(fams, G)])
+    return dict(G=G, W=W, deltas=deltas, fam_n=fam_n, inv_dmin=inv_dmin, step=step)
+
+
+def subset_multiplier(side):
+    nL = sum(1 for s in side if s < 0)
+    nR = sum(1 for s in side if s > 0)
+    return max(nL, nR)
+
+
+def run_frame(wl, keep=False, levels_only=None):
+    """Run the whole pipeline on a scenegen workload.  Returns the level-0
+    depth/normal/confidence plus, with keep=True, every intermediate per
+    level.  ``levels_only`` stops after the given level (for bounded runs)."""
+    p = wl["params"]
+    n = p["n_levels"]
+    K = np.asarray(wl["K"], np.float64)
+    ref = wl["ref"]
+    views = wl["views"]
+    side = np.asarray(wl["side"], np.int8)
+    m = subset_multiplier(wl["side"])
+    p1 = m * p["p1"]
+    lut = p2_lut(p1, p["p2_mode"], m * p["p2_fixed"], p["p2_alpha"], p["p2_beta"])
+    cw, chh = p["census_w"], p["census_h"]
+    pyr_ref = [np.asarray(ref["img"], np.uint8)]
+    pyr_views = [[np.asarray(v["img"], np.uint8)] for v in views]
+    for l in range(1, n):
+        pyr_ref.append(pyr_down(pyr_ref[-1]))
+        for pv in pyr_views:
+            pv.append(pyr_down(pv[-1]))
+    rel = [relative_pose(ref["R"], ref["t"], v["R"], v["t"]) for v in views]
+    out = {"levels": {}}
+    offs = None
+    dI = None
+    for l in range(n - 1, -1, -1):
+        Ki, Kl = kinv_level(K, l)
+        plan = level_plan(wl, l)
+        img = pyr_ref[l]
+        h, w = img.shape
+        sumG = sum(plan["G"])
+        H = np.zeros((len(views), sumG, 3, 3))
+        for k, (R, t) in enumerate(rel):
+            g0 = 0
+            for f, dl in enumerate(plan["deltas"]):
+                for j, dv in enumerate(dl):
+                    H[k, g0 + j] = homography(Kl, Ki, R, t, plan["fam_n"][f], dv)
+                g0 += len(dl)
+        ct = census(img, cw, chh)
+        top = l == n - 1
+        o = None if top or p["window_labels"] <= 0 else offs
+        S = cost_volume(ct, [pv[l] for pv in pyr_views], side, cw, chh, plan["G"], plan["W"], H, o)
+        use_dI = (not top) and p["sgm_variant"] == 1 and dI is not None
+        Sbar, _ = sgm(S, plan["W"], p1, lut, img, p["n_paths"], offs=o, dI=dI if use_dI else None)
+        fam_delta = np.concatenate(plan["deltas"])
+        label, fam, depth_raw = wta_refine(Sbar, plan["W"], plan["G"], plan["fam_n"], fam_delta, Ki, o)
+        depth = median5(depth_raw) if p["median"] else depth_raw
+        nraw = normals(depth, Ki)
+        nsm = normal_smooth(nraw, img, p["normal_radius"], p["normal_beta"])
+        conf = confidence(nsm, label, fam, plan["fam_n"], p["conf_rho_deg"])
+        rec = dict(depth=depth, normal=nsm, conf=conf, label=label, fam=fam)
+        if keep:
+            rec.update(S=S, Sbar=Sbar, depth_raw=depth_raw, normal_raw=nraw, ct=ct, offs=o,
+                       dI=dI if use_dI else None, H=H, plan=plan, img=img)
+        out["levels"][l] = rec
+        if levels_only is not None and l == levels_only:
+            break
+        if l > 0:
+            fh, fw = pyr_ref[l - 1].shape
+            dbar = upsample_nn(depth, fw, fh)
+            nbar = upsample_nn(nsm, fw, fh)
+            Ki_f, _ = kinv_level(K, l - 1)
+            plan_f = level_plan(wl, l - 1)
+            offs = window_offsets(dbar, Ki_f, plan_f["fam_n"], plan_f["inv_dmin"], plan_f["step"],
+                                  plan_f["G"], plan_f["W"])
+            dI = delta_i(dbar, nbar, Ki_f, plan_f["fam_n"], plan_f["step"]) if p["sgm_variant"] == 1 else None
+            if keep:
+                out["levels"][l]["seed"] = dict(dbar=dbar, nbar=nbar, offs=offs, dI=dI)
+    if 0 in out["levels"]:
+        lv = out["levels"][0]
+        out["depth"], out["normal"], out["conf"] = lv["depth"], lv["normal"], lv["conf"]
+    out["pyr_ref"] = pyr_ref
+    out["pyr_views"] = pyr_views
+    return out
