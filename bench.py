@@ -1,0 +1,150 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the FaSS-MVS hot path on one MI355X.
+
+One step = one whole coarse-to-fine frame (pyramid, reference census, fused
+warp+census+Hamming sweep, 8-path surface-aware SGM with fused WTA,
+refinement, median, normals, confidence, coarse-to-fine seeding) of the
+1920x1080 oblique UAV-shaped workload (reference + 4 views, 3 levels x 128
+planes, census 9x7), with the input images already resident in HBM.  Prints
+one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpx·hyp/s (sweep+SGM), frames/s, p50/p99 latency: served vs plain, 1 MI355X"
+PEAK_HBM_GBS = 8000.0
+# plain 32-bit VALU lane operations: 256 CUs x 64 lanes x 2.4 GHz
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+# algorithmic work of the sweep per (pixel, hypothesis, view): one compare per
+# census bit of the warped window, XOR + popcount of the 62-bit words (3), and
+# the warp of one sample (projective map + bilinear, about 15 operations)
+SWEEP_ALG_OPS_9x7 = 62 + 3 + 15
+# algorithmic bytes of SGM per (pixel, hypothesis): S read once per path (8 x
+# 1 B) plus the aggregate written and read once (2 x 2 B)
+SGM_ALG_BYTES = 12.0
+
+WORKLOADS = {
+    "config2": ("1920x1080 oblique urban scene, reference + 4 views (2 left, 2 right), 3 levels x 128 "
+                "fronto-parallel planes over [20, 400] m (window 128 below the top), census 9x7, "
+                "SGM^Pi-sn 8 paths, adaptive P2, parabola refinement, 5x5 median, normals, confidence"),
+    "config1": "160x120 reference + 2 views, 32 planes, census 5x5, 8-path SGM P1=8 P2=64, 1 level",
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the hot path does not shard across GPUs); got --gpus {args.gpus}",
+              file=sys.stderr)
+        return 2
+
+    import scenegen
+    import paper_2112_00821_amd as fm
+
+    wl = scenegen.make_workload(args.workload)
+    cfg = fm.config_from_params(wl["params"], profile=1)
+    h, w = wl["height"], wl["width"]
+    with fm.Handle(cfg) as hd:
+        ref = dict(wl["ref"], img=hd.upload(wl["ref"]["img"]))
+        views = [dict(v, img=hd.upload(v["img"])) for v in wl["views"]]
+        depth = hd.empty((h, w), np.float32)
+        normal = hd.empty((h, w, 3), np.float32)
+        conf = hd.empty((h, w), np.float32)
+
+        def step():
+            t = hd.submit_frame(ref, views, wl["side"], wl["K"], wl["families"], mem_kind=fm.MEM_DEVICE)
+            hd.poll(t, depth, normal, conf, mem_kind=fm.MEM_DEVICE, wait_ms=-1)
+
+        for _ in range(args.warmup):
+            step()
+        hd.synchronize()
+        hd.reset_stage_times()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            a = time.perf_counter()
+            step()
+            lat.append(time.perf_counter() - a)
+        hd.synchronize()
+        el = time.perf_counter() - t0
+        times = hd.stage_times()
+        work = hd.frame_work()
+
+    ms = el / args.steps * 1e3
+    hyp = work["pixel_hyp"]
+    value = hyp / 1e6 / (ms / 1e3)
+    sweep_ms = times["sweep"][0] / max(times["sweep"][1], 1)
+    sweep_launches = times["sweep"][1] / args.steps
+    sgm_ms = (times["sgm_dirs"][0] + times["sgm_wta"][0]) / args.steps
+    sweep_frame_ms = times["sweep"][0] / args.steps
+    ks_value = hyp / 1e6 / ((sweep_frame_ms + sgm_ms) / 1e3)
+    # dominant kernel and its roofline
+    if sweep_frame_ms >= sgm_ms:
+        units = work["pixel_hyp_views"] / sweep_launches
+        achieved = SWEEP_ALG_OPS_9x7 * units / (sweep_ms / 1e3) / 1e12
+        roof = {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": PEAK_VALU_TOPS,
+                "unit": "TOP/s", "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
+                "avg_launch_ms": sweep_ms, "alg_ops_per_px_hyp_view": SWEEP_ALG_OPS_9x7}
+    else:
+        achieved = SGM_ALG_BYTES * hyp / (sgm_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": "k_sgm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "stage_ms_per_frame": sgm_ms,
+                "alg_bytes_per_px_hyp": SGM_ALG_BYTES}
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpx·hyp/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8/u16 integer matching, f32 warp, f64 geometry", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "pixel_hyp_per_frame": hyp,
+                   "width": w, "height": h},
+        "frames_per_s": round(1e3 / ms, 2),
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 3), "mode": "plain per-frame pipeline"},
+        "sweep_sgm_only_value": round(ks_value, 1),
+        "stage_ms_per_frame": {k: round(v[0] / args.steps, 4) for k, v in times.items() if v[1]},
+        "sweep_label_inflation": round(work["sweep_evaluated"] / hyp, 4) if hyp else None,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out))
+    return 0
+
+
+def cpu_baseline(wl):
+    """The oracle, single-threaded, on a bounded sample of the same frame:
+    its coarsest pyramid level (every stage of that level)."""
+    import oracle
+    oracle.build()
+    top = wl["params"]["n_levels"] - 1
+    t0 = time.perf_counter()
+    out = oracle.run_frame(wl, keep=False, levels_only=top)
+    el = time.perf_counter() - t0
+    lv = out["levels"][top]
+    hh, ww = lv["depth"].shape
+    plan = oracle.level_plan(wl, top)
+    hyp = hh * ww * sum(plan["W"])
+    return {"value": round(hyp / 1e6 / el, 3), "unit": "Mpx·hyp/s", "cores": 1, "kind": "oracle",
+            "sample": f"coarsest level of the same frame ({ww}x{hh} x {sum(plan['W'])} planes, pyramid + "
+                      f"census + cost volume + 8-path SGM + refinement + median + normals + confidence), "
+                      f"{el:.1f} s single-threaded"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,284 @@
+/*
+ * fassmvs.h -- C ABI of the MI355X (gfx950) implementation of the FaSS-MVS
+ * hot path: hierarchical plane-sweep multi-image matching with a
+ * census-Hamming cost (Alg. 1 of the paper; Eq. homography) followed by
+ * surface-aware semi-global matching (Eq. sgm-path ... sgm-smooth-sn,
+ * Eq. p2-grad), winner-takes-all plane selection with sub-plane depth
+ * refinement, normal map (Eq. normal, normal-smooth) and geometric
+ * confidence (Eq. weight-normal), run coarse-to-fine over a Gaussian
+ * pyramid (pipeline overview; Eq. sampling_range).
+ *
+ * The library is self-contained: plain C types, no exceptions cross the
+ * boundary, every call returns a status.  Device memory is owned by the
+ * handle unless a pointer is documented as caller-owned device memory.
+ *
+ * Coordinate conventions shared by every call:
+ *  - images are row-major 8-bit grayscale; pixel (x, y) has its centre at
+ *    (x + 0.5, y + 0.5) in the coordinates K maps camera rays to;
+ *  - poses: x_cam = R x_world + t (R row-major), one intrinsic matrix K for
+ *    all images (upper triangular, K[8] == 1);
+ *  - a plane (n, delta) is { X : n^T X + delta = 0 } in reference-camera
+ *    coordinates, n a unit vector facing the camera (n[2] < 0);
+ *  - depth is the z coordinate in the reference camera; maps have the
+ *    reference image's size; normals are unit vectors in reference-camera
+ *    coordinates, xyz interleaved; invalid pixels get depth 0, normal 0 and
+ *    confidence 0.
+ */
+#ifndef FASSMVS_H
+#define FASSMVS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fassmvs_handle fassmvs_handle;
+typedef int32_t fassmvs_status;
+
+#define FASSMVS_OK 0
+#define FASSMVS_PENDING 1          /* frame still running on the device */
+#define FASSMVS_EINVAL (-1)        /* bad argument (sizes, poses, plane behind a camera, > 256 planes) */
+#define FASSMVS_EUNSUPPORTED (-2)  /* valid but not supported (census size, 8/16-bit cost bounds) */
+#define FASSMVS_ENOMEM (-3)        /* device allocation failed or frame exceeds the HBM budget */
+#define FASSMVS_EBUSY (-4)         /* a frame is already in flight on this handle; poll first */
+#define FASSMVS_EDEVICE (-5)       /* HIP runtime error; the handle is latched, see fassmvs_last_error */
+#define FASSMVS_ENOTFOUND (-6)     /* unknown or already consumed ticket */
+
+#define FASSMVS_MEM_HOST 0
+#define FASSMVS_MEM_DEVICE 1
+
+#define FASSMVS_MAX_VIEWS 8        /* matching images per bundle */
+#define FASSMVS_MAX_FAMILIES 8     /* plane orientations per frame */
+#define FASSMVS_MAX_LABELS 512     /* labels per pixel at one level (sum of family windows) */
+#define FASSMVS_MAX_TOP_PLANES 256 /* planes per family at the coarsest level (paper's cap) */
+#define FASSMVS_MAX_LEVELS 5
+
+/* Number of per-stage timers reported by fassmvs_stage_times. */
+#define FASSMVS_N_STAGES 12
+
+typedef struct {
+    int32_t n_levels;          /* pyramid height n, 1..5 (pipeline overview) */
+    int32_t census_w;          /* census window width, 5 or 9 (similarity-measure experiment) */
+    int32_t census_h;          /* census window height, 5 or 7 */
+    int32_t n_paths;           /* 8, or 4 (diagonals dropped) */
+    int32_t sgm_variant;       /* 0: SGM^Pi; 1: SGM^Pi-sn below the coarsest level */
+    int32_t p1;                /* P1 per matching image; scaled by m = max(|L|,|R|) */
+    int32_t p2_mode;           /* 0: fixed P2; 1: adaptive P2 (Eq. p2-grad) */
+    int32_t p2_fixed;          /* P2 per matching image in fixed mode (>= p1) */
+    double p2_alpha;           /* alpha of Eq. p2-grad (paper: 8) */
+    double p2_beta;            /* beta of Eq. p2-grad (paper: 10) */
+    int32_t window_labels;     /* labels per family and pixel below the coarsest level; 0: whole list */
+    int32_t median;            /* 1: 5x5 median on the depth map */
+    int32_t normal_radius;     /* smoothing window radius r (sigma = r), 1..4 */
+    double normal_beta;        /* beta of Eq. normal-smooth (paper: 10) */
+    double conf_rho_deg;       /* critical angle of Eq. weight-normal (paper: 60) */
+    int32_t device;            /* HIP device ordinal */
+    void *stream;              /* hipStream_t to run on; NULL: the handle creates its own */
+    uint64_t hbm_budget_bytes; /* device memory the handle may hold; 0: no limit */
+    int32_t profile;           /* 1: time every stage with HIP events */
+    int32_t keep_levels;       /* 1: keep per-level maps of the last frame (fassmvs_level_map) */
+    int32_t sgm_debug;         /* 1: write every path's costs and the full aggregate (tests) */
+} fassmvs_config;
+
+typedef struct {
+    const uint8_t *pixels;     /* host or device memory, see mem_kind */
+    int32_t width, height;
+    int32_t stride;            /* bytes between rows, >= width */
+    double R[9];               /* row-major rotation, x_cam = R x_world + t */
+    double t[3];
+} fassmvs_image;
+
+typedef struct {
+    double n[3];               /* unit normal in reference-camera coordinates, n[2] < 0 */
+    double delta_min;          /* nearest plane distance, > 0 */
+    double delta_max;          /* farthest plane distance, > delta_min */
+    int32_t count;             /* planes at the coarsest level (2..256); level l uses
+                                  count * 2^(n-1-l) planes uniform in 1/delta */
+} fassmvs_plane_family;
+
+/* Paper defaults: 8 paths, SGM^Pi, census 9x7, P1 24 (census 9x7 setting of
+ * the similarity-measure experiment), adaptive P2 with alpha 8 and beta 10,
+ * 5x5 median, normal radius 2, beta 10, rho 60 deg, 3 levels, window 128. */
+void fassmvs_config_default(fassmvs_config *cfg);
+
+/* Create a handle on cfg->device.  Validates the configuration (EINVAL /
+ * EUNSUPPORTED) and creates the stream when cfg->stream is NULL.  Device
+ * buffers are allocated lazily by the first frame and grow with the frame
+ * size.  *out receives the handle (NULL on failure). */
+fassmvs_status fassmvs_create(const fassmvs_config *cfg, fassmvs_handle **out);
+
+/* Enqueue one frame (the problem statement of the pipeline overview: a
+ * bundle of images with poses in, depth / normal / confidence maps of the
+ * reference image out).
+ *   ref, views: reference and n_views matching images, all of the
+ *     reference's size; pixel memory is host memory (copied before return)
+ *     or, with mem_kind FASSMVS_MEM_DEVICE, device memory read on the
+ *     handle's stream (the caller keeps it valid until poll returns OK).
+ *   view_side: per view -1 (before the reference in the sequence, left
+ *     subset) or +1 (after it, right subset) for the occlusion-robust
+ *     minimum of Alg. 1.
+ *   K: intrinsics of level 0 (row-major).
+ *   families, n_families: plane orientations and distance ranges.
+ *   ticket: receives the frame's ticket.
+ * One frame may be in flight per handle (EBUSY otherwise).  Errors:
+ * EINVAL (sizes, non-finite pose, plane list, a camera centre behind the
+ * nearest plane), EUNSUPPORTED (cost or aggregate overflow bounds),
+ * ENOMEM, EDEVICE. */
+fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref, const fassmvs_image *views,
+                                    const int8_t *view_side, int32_t n_views, const double K[9],
+                                    const fassmvs_plane_family *families, int32_t n_families,
+                                    int32_t mem_kind, uint64_t *ticket);
+
+/* Collect a frame's maps.  depth: W*H floats; normal: W*H*3 floats; confidence:
+ * W*H floats in [0, 1]; any may be NULL.  mem_kind says whether the output
+ * pointers are host or device memory.  wait_ms: 0 non-blocking, -1 blocking,
+ * else a bound in milliseconds.  Returns PENDING while the frame runs, OK
+ * once the maps are written (the ticket is then consumed), ENOTFOUND for an
+ * unknown ticket. */
+fassmvs_status fassmvs_poll(fassmvs_handle *h, uint64_t ticket, float *depth, float *normal, float *confidence,
+                            int32_t mem_kind, int32_t wait_ms);
+
+/* Wait for any frame in flight and release every resource of the handle. */
+void fassmvs_destroy(fassmvs_handle *h);
+
+/* Last error message of the handle (owned by the handle, valid until the
+ * next call on it); "" if none.  h may be NULL (then: the last create error). */
+const char *fassmvs_last_error(const fassmvs_handle *h);
+
+/* Accumulated device time per stage in milliseconds and the number of
+ * timed launches (cfg.profile = 1), for stage ids 0..n-1 (see
+ * fassmvs_stage_name); reset with fassmvs_reset_stage_times. */
+fassmvs_status fassmvs_stage_times(fassmvs_handle *h, double *ms, int32_t *counts, int32_t n);
+fassmvs_status fassmvs_reset_stage_times(fassmvs_handle *h);
+const char *fassmvs_stage_name(int32_t stage);
+
+/* Work units of the last frame, for throughput and roofline figures:
+ * out[0] = sum over levels of pixels x labels (pixel-hypotheses),
+ * out[1] = pixel-hypotheses x matching views, out[2] = labels actually
+ * evaluated by the sweep (pixel-hypotheses including tile-union work),
+ * out[3] = bytes the SGM stage moves by design. */
+fassmvs_status fassmvs_frame_work(fassmvs_handle *h, double *out, int32_t n);
+
+/* Copy a per-level map of the last completed frame (cfg.keep_levels = 1)
+ * into caller-owned device memory dst of dst_bytes.  what: 0 depth (float
+ * W*H, after the median), 1 raw depth (before the median), 2 normal (float
+ * W*H*3), 3 confidence, 4 global plane label (int32, -1 invalid), 5 family
+ * (int32), 6 window offsets ([F][H][W] int32, levels below the coarsest),
+ * 7 surface-normal offsets ([8][H][W][F] int8), 8 level width/height
+ * (2 x int32 written to dst as host memory), 9 cost volume S of level 0
+ * ([H][W][D] uint8), 10+r path costs of direction r at level 0 ([H][W][D]
+ * uint16),
+ * 20 reference census of level 0 ([H][W] uint64), 30+i pyramid image i of
+ * the level (0 reference, 1.. views; [H][W] uint8). */
+fassmvs_status fassmvs_level_map(fassmvs_handle *h, int32_t level, int32_t what, void *dst, size_t dst_bytes);
+
+/* ---------------------------------------------------------------------
+ * Device-memory plumbing for callers without their own HIP allocator
+ * (tests, benchmark).  All run on the handle's device and stream.
+ * --------------------------------------------------------------------- */
+
+/* Allocate / free device memory (hipMalloc / hipFree). */
+fassmvs_status fassmvs_device_alloc(fassmvs_handle *h, size_t bytes, void **ptr);
+fassmvs_status fassmvs_device_free(fassmvs_handle *h, void *ptr);
+
+/* Copy bytes; kind 0 host->device, 1 device->host, 2 device->device.
+ * Returns when the copy has completed (the handle's stream is drained first). */
+fassmvs_status fassmvs_memcpy(fassmvs_handle *h, void *dst, const void *src, size_t bytes, int32_t kind);
+
+/* Fill device memory with a byte value (a fill kernel, not a memset node). */
+fassmvs_status fassmvs_fill(fassmvs_handle *h, void *dst, uint8_t value, size_t bytes);
+
+/* Wait until everything enqueued on the handle's stream has completed. */
+fassmvs_status fassmvs_synchronize(fassmvs_handle *h);
+
+/* ---------------------------------------------------------------------
+ * Stage entry points.  Each runs one kernel of the frame pipeline on
+ * caller-owned device buffers (dense, row-major, no padding) and returns
+ * when it has completed.  They exist so that every stage can be checked on
+ * its own inputs; the frame pipeline uses the same kernels.
+ * --------------------------------------------------------------------- */
+
+/* Gaussian pyramid step (pipeline overview): 3x3 blur with taps
+ * (70,116,70)/256, replicate border, rounding after each pass, then the mean
+ * of each 2x2 block.  src w*h, dst (w/2)*(h/2). */
+fassmvs_status fassmvs_stage_pyr_down(fassmvs_handle *h, const uint8_t *src, int32_t w, int32_t hgt, uint8_t *dst);
+
+/* Census transform of an 8-bit image (Alg. 1 cost): bit (nbits-1-b) of the
+ * result is [I(q_b) < I(p)] for the b-th window position q_b in row-major
+ * order, centre skipped, replicate border.  cw x ch odd, cw*ch-1 <= 64. */
+fassmvs_status fassmvs_stage_census(fassmvs_handle *h, const uint8_t *img, int32_t w, int32_t hgt, int32_t cw,
+                                    int32_t ch, uint64_t *out);
+
+/* Warp one matching image onto the reference grid (Alg. 1): the value at
+ * reference pixel q is the bilinear, clamp-to-edge sample of src at
+ * H (q + 0.5) - 0.5 on the 0..255 scale (float).  H row-major (host). */
+fassmvs_status fassmvs_stage_warp(fassmvs_handle *h, const uint8_t *src, int32_t sw, int32_t sh, const double H[9],
+                                  int32_t rw, int32_t rh, float *out);
+
+/* Cost volume (Alg. 1): S[y][x][l] (uint8) for every reference pixel and
+ * label l of the concatenated families, each family f contributing W[f]
+ * labels from global index offs[f][y][x] (or all of its G[f] planes when
+ * offs is NULL).  views: n_views device pointers (host array) to w*h
+ * matching images; H: host array [n_views][sum G][9]; ct_ref from
+ * fassmvs_stage_census.  With warped != NULL the warp is skipped and the
+ * pre-warped float images [n_views][sum G][h][w] are read instead. */
+fassmvs_status fassmvs_stage_cost(fassmvs_handle *h, int32_t w, int32_t hgt, const uint64_t *ct_ref,
+                                  int32_t n_views, const uint8_t *const *views, const int8_t *view_side,
+                                  int32_t cw, int32_t ch, int32_t n_fam, const int32_t *G, const int32_t *W,
+                                  const double *H, const int32_t *offs, const float *warped, uint8_t *S);
+
+/* Semi-global aggregation and winner-takes-all (Eq. sgm-path, sgm-aggr,
+ * sgm-wta with the smoothness terms of Eq. sgm-smooth-fp / sgm-smooth-sn).
+ *   S [h][w][D] uint8, D = sum W; offs [F][h][w] int32 or NULL; dI
+ *   [8][h][w][F] int8 or NULL; ref [h][w] level image for P2 = lut[|dI|];
+ *   lut: host int32[256]; p1: effective P1.
+ * Outputs (any may be NULL): Lr [n_paths][h][w][D] uint16 per-path costs;
+ * Sbar [h][w][D] uint16 aggregate; wta [h][w] uint16 winning label (local,
+ * smallest on ties); c3 [h][w][3] uint16 aggregate at winner-1, winner,
+ * winner+1 (0xFFFF where the neighbour is outside the family's window). */
+fassmvs_status fassmvs_stage_sgm(fassmvs_handle *h, int32_t w, int32_t hgt, int32_t n_fam, const int32_t *W,
+                                 const uint8_t *S, const int32_t *offs, const int8_t *dI, const uint8_t *ref,
+                                 int32_t p1, const int32_t *lut, int32_t n_paths, uint16_t *Lr, uint16_t *Sbar,
+                                 uint16_t *wta, uint16_t *c3);
+
+/* Depth of the winning plane and parabola refinement (depth extraction for
+ * SGM^Pi; depth refinement): from wta and c3 of fassmvs_stage_sgm.  Host
+ * arrays: fam_n [F][3], fam_delta (concatenated level plane lists, sum G),
+ * Kinv [9] of the level.  Outputs label (global, -1 invalid), fam, depth. */
+fassmvs_status fassmvs_stage_refine(fassmvs_handle *h, int32_t w, int32_t hgt, int32_t n_fam, const int32_t *W,
+                                    const int32_t *G, const int32_t *offs, const uint16_t *wta, const uint16_t *c3,
+                                    const double *fam_n, const double *fam_delta, const double *Kinv,
+                                    int32_t *label, int32_t *fam, float *depth);
+
+/* 5x5 median (pipeline overview), replicate border, 13th of 25. */
+fassmvs_status fassmvs_stage_median(fassmvs_handle *h, const float *in, int32_t w, int32_t hgt, float *out);
+
+/* Normals (Sec. extraction of surface normals), then appearance-weighted
+ * smoothing (Eq. normal, normal-smooth) and confidence (Eq. weight-normal).
+ * depth [h][w]; img [h][w] level reference image; label/fam from
+ * fassmvs_stage_refine; Kinv, fam_n host arrays.  Outputs nraw (may be NULL),
+ * normal [h][w][3], conf [h][w]. */
+fassmvs_status fassmvs_stage_normals(fassmvs_handle *h, const float *depth, const uint8_t *img, int32_t w,
+                                     int32_t hgt, const double *Kinv, int32_t radius, double beta,
+                                     const int32_t *label, const int32_t *fam, int32_t n_fam,
+                                     const double *fam_n, double rho_deg, float *nraw, float *normal,
+                                     float *conf);
+
+/* Coarse-to-fine seeds (pipeline overview; dynamic cost volume;
+ * Eq. sgm-smooth-sn): nearest-neighbour upsampling of the coarse depth and
+ * normal (cw x ch) to the fine level (fw x fh), the per-family sampling
+ * windows and, when dI != NULL, the surface-normal index offsets for the 8
+ * path directions.  Kinv: fine level; inv_dmin, step, G, W per family. */
+fassmvs_status fassmvs_stage_seed(fassmvs_handle *h, const float *depth_c, const float *normal_c, int32_t cw,
+                                  int32_t ch, int32_t fw, int32_t fh, const double *Kinv, int32_t n_fam,
+                                  const double *fam_n, const double *inv_dmin, const double *step,
+                                  const int32_t *G, const int32_t *W, float *dbar, float *nbar, int32_t *offs,
+                                  int8_t *dI);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASSMVS_H */

@@ -68,6 +68,7 @@ def _declare(L):
         "or_census_u8": (i, [vp, i, i, i, i, vp]),
         "or_cost_volume": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, vp, vp, vp]),
         "or_cost_sample": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, i, i, i, i]),
+        "or_cost_pixels": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, vp, vp, i, vp, vp]),
         "or_sgm": (i, [i, i, i, vp, vp, vp, vp, i, vp, vp, i, vp, vp]),
         "or_wta_refine": (None, [i, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "or_median5": (None, [vp, i, i, vp]),
@@ -190,6 +191,22 @@ def cost_sample(ct_ref, views, side, cw, ch, G, H, f, g, x, y):
     return lib().or_cost_sample(w, h, _p(_c(ct_ref, np.uint64)), len(arrs), C.cast(ptrs, C.c_void_p),
                                 _p(_c(side, np.int8)), cw, ch, len(G), _p(G), _p(_c(H, np.float64)),
                                 int(f), int(g), int(x), int(y))
+
+
+def cost_pixels(ct_ref, views, side, cw, ch, G, W, H, xy, offs=None):
+    """Cost vectors [n][sum W] of the pixels xy ([n][2] as x, y)."""
+    h, w = ct_ref.shape
+    G = np.asarray(G, np.int32)
+    W = np.asarray(W, np.int32)
+    xy = _c(xy, np.int32)
+    arrs, ptrs = _view_ptrs(views)
+    out = np.zeros((len(xy), int(W.sum())), np.uint8)
+    r = lib().or_cost_pixels(w, h, _p(_c(ct_ref, np.uint64)), len(arrs), C.cast(ptrs, C.c_void_p),
+                             _p(_c(side, np.int8)), cw, ch, len(G), _p(G), _p(W), _p(_c(H, np.float64)),
+                             _p(_c(offs, np.int32) if offs is not None else None), len(xy), _p(xy), _p(out))
+    if r != 0:
+        raise ValueError("cost_pixels failed (%d)" % r)
+    return out
 
 
 def sgm(S, W, p1, lut, ref, n_paths, offs=None, dI=None, want_sbar=True, want_lr=False):

@@ -360,6 +360,31 @@ int or_cost_sample(int w, int h, const uint64_t* ct_ref, int n_views, const uint
     return combine_lr(sL, sR, nL, nR);
 }
 
+// The cost vectors of a list of pixels (same definition as or_cost_volume,
+// evaluated pixel by pixel through or_cost_sample): out[i][label] for pixel
+// (xy[2i], xy[2i+1]) with the pixel's window offsets (offs NULL: full lists).
+int or_cost_pixels(int w, int h, const uint64_t* ct_ref, int n_views, const uint8_t* const* views,
+                   const int8_t* side, int cw, int ch, int n_fam, const int* G, const int* W,
+                   const double* H, const int32_t* offs, int n_pix, const int32_t* xy, uint8_t* out) {
+    int D = 0;
+    for (int f = 0; f < n_fam; ++f) D += W[f];
+    size_t N = (size_t)w * h;
+    for (int i = 0; i < n_pix; ++i) {
+        int x = xy[2 * i], y = xy[2 * i + 1];
+        if (x < 0 || x >= w || y < 0 || y >= h) return -1;
+        int l = 0;
+        for (int f = 0; f < n_fam; ++f) {
+            int o = offs ? offs[(size_t)f * N + (size_t)y * w + x] : 0;
+            for (int j = 0; j < W[f]; ++j, ++l) {
+                int c = or_cost_sample(w, h, ct_ref, n_views, views, side, cw, ch, n_fam, G, H, f, o + j, x, y);
+                if (c > 255) return -2;
+                out[(size_t)i * D + l] = (uint8_t)c;
+            }
+        }
+    }
+    return 0;
+}
+
 // ---------------------------------------------------------------------------
 // Semi-global aggregation (Eq. sgm-path, sgm-smooth, sgm-aggr for SGM^Pi in
 // Eq. xsgm / sgm-smooth-fp and the surface-normal offset of

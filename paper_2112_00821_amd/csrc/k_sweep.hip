@@ -1,0 +1,305 @@
+// Fused plane-sweep matching on gfx950 (Alg. 1 of the paper): for a tile of
+// reference pixels and each plane label, every matching view is warped onto
+// the tile (plus the census halo) into LDS, the census of the warped view is
+// formed in LDS, its Hamming distance to the reference census taken with
+// v_bcnt, the per-side sums combined by the occlusion-robust minimum, and
+// the cost written to the label-innermost uint8 volume S[y][x][label].
+//
+// Tile 64 x 32 pixels, 256 threads = 4 waves; thread (tx, ty) owns column
+// tx and rows 8ty..8ty+7, so every LDS row read serves up to eight census
+// windows.  The warp of a thread's samples runs in phases (coordinates, all
+// gathers in flight, interpolation) so gather latency overlaps.  The label range of a block is the union of its pixels' windows
+// (dynamic cost volume); pixels whose window misses a label skip the store.
+// Warped values are double-buffered so one barrier per (label, view) pair
+// suffices.  Blocks are remapped so that neighbouring tiles share an XCD's L2.
+#include "dev_common.hpp"
+#include "kernels.hpp"
+
+#include <climits>
+
+namespace fmvs {
+
+namespace {
+constexpr int TW = 64, NT = 256;
+
+__device__ __forceinline__ uint32_t insert_sign(uint32_t acc, float v, float c) {
+    // (acc << 1) | [v < c]: the sign of v - c (exact for distinct floats,
+    // +0 when equal) shifted in through alignbit
+    return __builtin_amdgcn_alignbit(acc, __float_as_uint(v - c), 31);
+}
+
+__device__ __forceinline__ int combine_lr(int sL, int sR, int nL, int nR, int m) {
+    if (nL == m && nR == m) return sL < sR ? sL : sR;
+    int best = INT_MAX;
+    if (nL > 0) best = (sL * m) / nL;
+    if (nR > 0) {
+        int v = (sR * m) / nR;
+        best = v < best ? v : best;
+    }
+    return best;
+}
+
+// Warp the region [rx0, rx0 + RW) x [ry0, ...) of the reference grid
+// (coordinates clamped to the image, so the halo replicates the border)
+// into LDS.  Same arithmetic as warp_sample, in three phases per thread:
+// all coordinates, then all gathers, then all interpolations.
+template <int RW, int NS>
+__device__ __forceinline__ void warp_region(float *buf, const uint8_t *__restrict__ src, int w, int h, int rx0, int ry0,
+                                            int tid, double h0, double h1, double h2, double h3, double h4, double h5,
+                                            double h6, double h7, double h8) {
+    constexpr int NPT = (NS + NT - 1) / NT;
+    constexpr int WB = 4;   // samples per batch: 4 x 4 gathers in flight
+    constexpr int DRY = NT / RW, DRX = NT % RW;
+    int ry = tid / RW, rx = tid - (tid / RW) * RW;
+#pragma unroll 1
+    for (int i0 = 0; i0 < NPT; i0 += WB) {
+        float ax[WB], ay[WB];
+        uint32_t o00[WB], dxo[WB], dyo[WB];
+        uint32_t g[WB][4];
+#pragma unroll
+        for (int i = 0; i < WB; ++i) {
+            const double qx = (double)min(max(rx0 + rx, 0), w - 1) + 0.5;
+            const double qy = (double)min(max(ry0 + ry, 0), h - 1) + 0.5;
+            double hx = h0 * qx + h1 * qy + h2;
+            double hy = h3 * qx + h4 * qy + h5;
+            double hz = h6 * qx + h7 * qy + h8;
+            double inv = 1.0 / hz;
+            double sx = hz > 0.0 ? hx * inv - 0.5 : -1.0;
+            double sy = hz > 0.0 ? hy * inv - 0.5 : -1.0;
+            sx = fmin(fmax(sx, -1.0), (double)w);
+            sy = fmin(fmax(sy, -1.0), (double)h);
+            const double fx0 = floor(sx), fy0 = floor(sy);
+            const int x0 = (int)fx0, y0 = (int)fy0;
+            ax[i] = (float)(sx - fx0);
+            ay[i] = (float)(sy - fy0);
+            const int xa = min(max(x0, 0), w - 1), xb = min(max(x0 + 1, 0), w - 1);
+            const int ya = min(max(y0, 0), h - 1), yb = min(max(y0 + 1, 0), h - 1);
+            o00[i] = (uint32_t)(ya * w + xa);
+            dxo[i] = (uint32_t)(xb - xa);
+            dyo[i] = (uint32_t)((yb - ya) * w);
+            rx += DRX;
+            ry += DRY;
+            if (rx >= RW) {
+                rx -= RW;
+                ry += 1;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < WB; ++i) {
+            const bool act = i0 + i < NPT && tid + (i0 + i) * NT < NS;
+            const uint8_t *pa = src + o00[i];
+            g[i][0] = act ? pa[0] : 0u;
+            g[i][1] = act ? pa[dxo[i]] : 0u;
+            g[i][2] = act ? pa[dyo[i]] : 0u;
+            g[i][3] = act ? pa[dyo[i] + dxo[i]] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < WB; ++i) {
+            if (i0 + i < NPT && tid + (i0 + i) * NT < NS) {
+                const float i00 = (float)g[i][0], i10 = (float)g[i][1], i01 = (float)g[i][2], i11 = (float)g[i][3];
+                const float top = i00 + ax[i] * (i10 - i00);
+                const float bot = i01 + ax[i] * (i11 - i01);
+                buf[tid + (i0 + i) * NT] = top + ay[i] * (bot - top);
+            }
+        }
+    }
+}
+}  // namespace
+
+template <int CW, int CH, int RPT, bool WARPED>
+__global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
+    constexpr int TH = 4 * RPT;
+    constexpr int RX = CW / 2, RY = CH / 2;
+    constexpr int RW = TW + 2 * RX, RH = TH + 2 * RY;
+    constexpr int NB = CW * CH - 1;
+    constexpr int NHI = NB > 32 ? NB - 32 : 0;
+    constexpr int NS = RW * RH;
+    __shared__ float wbuf[2][NS];
+    __shared__ int s_lo[kMaxFam], s_hi[kMaxFam];
+
+    // XCD-aware remap: hardware dispatches workgroup b to XCD b % 8; give
+    // each XCD a contiguous range of logical work items
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int q = nb >> 3, r8 = nb & 7, xcd = b & 7, slot = b >> 3;
+    const int logical = xcd * q + min(xcd, r8) + slot;
+    const int chunk = logical % a.n_chunks;
+    const int tile = logical / a.n_chunks;
+    const int x0 = (tile % a.tiles_x) * TW;
+    const int y0 = (tile / a.tiles_x) * TH;
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 63, ty = tid >> 6;
+    const int x = x0 + tx;
+    const size_t N = (size_t)a.w * a.h;
+
+    if (tid < kMaxFam) {
+        s_lo[tid] = INT_MAX;
+        s_hi[tid] = INT_MIN;
+    }
+    __syncthreads();
+
+    uint32_t ref_hi[RPT], ref_lo[RPT];
+    bool valid[RPT];
+    uint32_t pix[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        int y = y0 + ty * RPT + j;
+        valid[j] = x < a.w && y < a.h;
+        pix[j] = valid[j] ? (uint32_t)(y * a.w + x) : 0u;
+        uint64_t ct = valid[j] ? a.ct_ref[pix[j]] : 0;
+        ref_hi[j] = (uint32_t)(ct >> 32);
+        ref_lo[j] = (uint32_t)ct;
+        if (valid[j]) {
+            for (int f = 0; f < a.n_fam; ++f) {
+                int o = a.offs ? a.offs[(size_t)f * N + pix[j]] : 0;
+                atomicMin(&s_lo[f], o);
+                atomicMax(&s_hi[f], o + a.W[f]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // this block's share of the concatenated union of label ranges
+    int total = 0;
+    for (int f = 0; f < a.n_fam; ++f) total += s_hi[f] > s_lo[f] ? s_hi[f] - s_lo[f] : 0;
+    const int per = (total + a.n_chunks - 1) / a.n_chunks;
+    const int pos0 = chunk * per;
+    const int pos1 = min(total, pos0 + per);
+    if (pos0 >= pos1) return;
+    if (a.work && tid == 0) {
+        int nv = min(TW, a.w - x0) * min(TH, a.h - y0);
+        atomicAdd(a.work, (unsigned long long)(pos1 - pos0) * (unsigned long long)nv);
+    }
+
+    int f = 0, fbase = 0;
+    while (f < a.n_fam && pos0 >= fbase + (s_hi[f] - s_lo[f])) {
+        fbase += s_hi[f] - s_lo[f];
+        ++f;
+    }
+    int g = s_lo[f] + (pos0 - fbase);
+    int off[RPT];   // window offsets of the current family
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) off[j] = (a.offs && valid[j]) ? a.offs[(size_t)f * N + pix[j]] : 0;
+
+    int it = 0;
+    for (int pos = pos0; pos < pos1; ++pos) {
+        int sL[RPT], sR[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) sL[j] = sR[j] = 0;
+        const size_t lab = (size_t)a.goff[f] + g;
+        for (int k = 0; k < a.n_views; ++k, ++it) {
+            float *buf = wbuf[it & 1];
+            const size_t hk = (size_t)k * a.sumG + lab;
+            if (WARPED) {
+                const float *src = a.warped + hk * N;
+                for (int s = tid; s < NS; s += NT) {
+                    int rx = s % RW, ry = s / RW;
+                    int qx = clampi(x0 - RX + rx, 0, a.w - 1), qy = clampi(y0 - RY + ry, 0, a.h - 1);
+                    buf[s] = src[(size_t)qy * a.w + qx];
+                }
+            } else {
+                const double *Hm = a.H + hk * 9;
+                const double h0 = Hm[0], h1 = Hm[1], h2 = Hm[2], h3 = Hm[3], h4 = Hm[4], h5 = Hm[5], h6 = Hm[6],
+                             h7 = Hm[7], h8 = Hm[8];
+                const uint8_t *src = a.views[k];
+                warp_region<RW, NS>(buf, src, a.w, a.h, x0 - RX, y0 - RY, tid, h0, h1, h2, h3, h4, h5, h6, h7, h8);
+            }
+            __syncthreads();
+            // census of the warped view for this thread's four pixels
+            const float *base = buf + (ty * RPT) * RW + tx;
+            float c[RPT];
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) c[j] = base[(j + RY) * RW + RX];
+            uint32_t hi[RPT], lo[RPT];
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) hi[j] = lo[j] = 0;
+#pragma unroll
+            for (int rr = 0; rr < RPT + 2 * RY; ++rr) {
+                float v[CW];
+#pragma unroll
+                for (int cx = 0; cx < CW; ++cx) v[cx] = base[rr * RW + cx];
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) {
+                    const int wy = rr - j;
+                    if (wy < 0 || wy >= CH) continue;
+#pragma unroll
+                    for (int cx = 0; cx < CW; ++cx) {
+                        if (wy == RY && cx == RX) continue;
+                        const int bpos = wy * CW + cx - ((wy > RY || (wy == RY && cx > RX)) ? 1 : 0);
+                        if (bpos < NHI)
+                            hi[j] = insert_sign(hi[j], v[cx], c[j]);
+                        else
+                            lo[j] = insert_sign(lo[j], v[cx], c[j]);
+                    }
+                }
+            }
+            const bool left = a.side[k] < 0;
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                int cst = __popc(hi[j] ^ ref_hi[j]) + __popc(lo[j] ^ ref_lo[j]);
+                if (left) sL[j] += cst; else sR[j] += cst;
+            }
+        }
+        // store the combined cost where this label lies in the pixel's window
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            int o = off[j];
+            if (valid[j] && g >= o && g < o + a.W[f]) {
+                int cst = combine_lr(sL[j], sR[j], a.nL, a.nR, a.m);
+                a.S[(size_t)pix[j] * a.D + a.foff[f] + (g - o)] = (uint8_t)cst;
+            }
+        }
+        if (++g >= s_hi[f]) {
+            ++f;
+            while (f < a.n_fam && s_hi[f] <= s_lo[f]) ++f;
+            if (f < a.n_fam) {
+                g = s_lo[f];
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) off[j] = (a.offs && valid[j]) ? a.offs[(size_t)f * N + pix[j]] : 0;
+            }
+        }
+    }
+}
+
+hipError_t launch_sweep(const SweepArgs &a0, hipStream_t s) {
+    SweepArgs a = a0;
+    // rows per thread (tile height / 4): 8 halves the halo and the LDS reads
+    // per pixel, 4 keeps more waves resident
+    int rpt = a.rows_per_thread == 4 ? 4 : 8;
+    const int th = 4 * rpt;
+    a.tiles_x = (a.w + TW - 1) / TW;
+    a.tiles_y = (a.h + th - 1) / th;
+    int tiles = a.tiles_x * a.tiles_y;
+    if (tiles == 0) return hipSuccess;
+    if (a.n_chunks <= 0) {
+        // enough work items to give every CU several blocks
+        int want = (2048 + tiles - 1) / tiles;
+        int maxc = (a.D + 7) / 8;
+        a.n_chunks = want < 1 ? 1 : (want > maxc ? maxc : want);
+    }
+    dim3 grid((unsigned)(tiles * a.n_chunks));
+#define FMVS_SWEEP(CWv, CHv)                                                                     \
+    if (a.cw == CWv && a.ch == CHv) {                                                            \
+        if (rpt == 4) {                                                                          \
+            if (a.warped)                                                                        \
+                hipLaunchKernelGGL((k_sweep<CWv, CHv, 4, true>), grid, dim3(NT), 0, s, a);       \
+            else                                                                                 \
+                hipLaunchKernelGGL((k_sweep<CWv, CHv, 4, false>), grid, dim3(NT), 0, s, a);      \
+        } else {                                                                                 \
+            if (a.warped)                                                                        \
+                hipLaunchKernelGGL((k_sweep<CWv, CHv, 8, true>), grid, dim3(NT), 0, s, a);       \
+            else                                                                                 \
+                hipLaunchKernelGGL((k_sweep<CWv, CHv, 8, false>), grid, dim3(NT), 0, s, a);      \
+        }                                                                                        \
+        return hipGetLastError();                                                                \
+    }
+    FMVS_SWEEP(5, 5)
+    FMVS_SWEEP(9, 7)
+    FMVS_SWEEP(7, 7)
+    FMVS_SWEEP(3, 3)
+#undef FMVS_SWEEP
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fmvs

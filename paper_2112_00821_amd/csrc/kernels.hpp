@@ -1,0 +1,118 @@
+// Internal interface between the FaSS-MVS host runtime and its gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fmvs {
+
+constexpr int kMaxViews = 8;
+constexpr int kMaxFam = 8;
+constexpr int kMaxLabels = 512;
+constexpr int kNumDirs = 8;
+
+// Path directions r (step p -> p + r): (1,0) (-1,0) (0,1) (0,-1) (1,1)
+// (-1,-1) (1,-1) (-1,1); four-path SGM uses the first four.
+__host__ __device__ inline int dir_dx(int r) {
+    const int t[8] = {1, -1, 0, 0, 1, -1, 1, -1};
+    return t[r];
+}
+__host__ __device__ inline int dir_dy(int r) {
+    const int t[8] = {0, 0, 1, -1, 1, -1, -1, 1};
+    return t[r];
+}
+
+// ---------------------------------------------------------------- sweep
+struct SweepArgs {
+    int w, h;                 // reference level size (views have the same size)
+    int cw, ch;               // census window
+    int n_views, nL, nR, m;
+    const uint8_t *views[kMaxViews];
+    int side[kMaxViews];
+    const uint64_t *ct_ref;   // [h][w]
+    int n_fam, D, sumG;
+    int G[kMaxFam], W[kMaxFam], foff[kMaxFam], goff[kMaxFam];
+    const double *H;          // [n_views][sumG][9]
+    const int32_t *offs;      // [n_fam][h][w] or nullptr (full lists)
+    const float *warped;      // [n_views][sumG][h][w] or nullptr
+    uint8_t *S;               // [h][w][D]
+    int tiles_x, tiles_y, n_chunks;
+    int rows_per_thread;      // 4 (tile 64x16) or 8 (tile 64x32)
+    unsigned long long *work; // optional counter of evaluated (pixel, label) pairs
+};
+hipError_t launch_sweep(const SweepArgs &a, hipStream_t s);
+
+// ---------------------------------------------------------------- sgm
+struct SgmArgs {
+    int w, h, D;
+    int n_fam;
+    int W[kMaxFam], foff[kMaxFam];
+    const uint8_t *S;         // [h][w][D]
+    const int32_t *offs;      // [n_fam][h][w] or nullptr
+    const int8_t *dI;         // [8][h][w][n_fam] or nullptr
+    const uint8_t *ref;       // [h][w]
+    int p1;
+    int lut[256];
+    // directions run by this launch and where each writes its path costs
+    int n_dirs;
+    int dirs[8];
+    uint16_t *out[8];         // [h][w][D] per launched direction (write mode)
+    int path_begin[9];        // prefix sum of path counts over the launched directions
+    // final mode: sum the finished directions' buffers, take the argmin
+    int final_mode;
+    int n_in;
+    const uint16_t *in[8];
+    uint16_t *wta;            // [h][w]
+    uint16_t *c3;             // [h][w][3]
+};
+int sgm_paths(int dir, int w, int h);
+hipError_t launch_sgm(const SgmArgs &a, hipStream_t s);
+hipError_t launch_sum_u16(const uint16_t *const *bufs, int n, size_t count, uint16_t *out, hipStream_t s);
+
+// ---------------------------------------------------------------- image stages
+hipError_t launch_pyr_down(const uint8_t *src, int w, int h, int stride, uint8_t *dst, hipStream_t s);
+hipError_t launch_census(const uint8_t *img, int w, int h, int cw, int ch, uint64_t *out, hipStream_t s);
+hipError_t launch_warp(const uint8_t *src, int sw, int sh, const double *dH, int rw, int rh, float *out,
+                       hipStream_t s);
+
+struct RefineArgs {
+    int w, h, n_fam;
+    int W[kMaxFam], G[kMaxFam], foff[kMaxFam], goff[kMaxFam];
+    double fam_n[kMaxFam][3];
+    double Kinv[9];
+    const double *delta;      // device, concatenated lists (sumG)
+    const int32_t *offs;
+    const uint16_t *wta, *c3;
+    int32_t *label, *fam;
+    float *depth;
+};
+hipError_t launch_refine(const RefineArgs &a, hipStream_t s);
+hipError_t launch_median5(const float *in, int w, int h, float *out, hipStream_t s);
+
+struct NormalArgs {
+    int w, h, radius;
+    double beta, cos_rho;
+    double Kinv[9];
+    int n_fam;
+    double fam_n[kMaxFam][3];
+    const float *depth;
+    const uint8_t *img;
+    const int32_t *label, *fam;
+    float *nraw, *normal, *conf;
+};
+hipError_t launch_normals(const NormalArgs &a, hipStream_t s);
+
+struct SeedArgs {
+    int cw, ch, fw, fh, n_fam;
+    double Kinv[9];
+    double fam_n[kMaxFam][3];
+    double inv_dmin[kMaxFam], step[kMaxFam];
+    int G[kMaxFam], W[kMaxFam];
+    const float *depth_c, *normal_c;
+    float *dbar, *nbar;
+    int32_t *offs;
+    int8_t *dI;
+};
+hipError_t launch_seed(const SeedArgs &a, hipStream_t s);
+
+}  // namespace fmvs

@@ -1,0 +1,1306 @@
+// Host runtime of the FaSS-MVS library: handle, argument validation,
+// per-frame planning (relative poses, level intrinsics, plane lists,
+// homographies and the P2 table in double precision), device buffers, the
+// coarse-to-fine level loop on one HIP stream, polling, stage timers and the
+// stage entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/fassmvs.h"
+#include "kernels.hpp"
+
+using namespace fmvs;
+
+namespace {
+
+enum Stage {
+    ST_UPLOAD = 0, ST_PYR, ST_CENSUS, ST_SWEEP, ST_SGM_DIRS, ST_SGM_WTA, ST_REFINE, ST_MEDIAN,
+    ST_NORMALS, ST_SEED, ST_OUTPUT, ST_SGM_DEBUG, ST_COUNT
+};
+static_assert(ST_COUNT == FASSMVS_N_STAGES, "stage count");
+const char *kStageNames[ST_COUNT] = {"upload", "pyramid", "census", "sweep", "sgm_dirs", "sgm_wta",
+                                     "refine", "median", "normals", "seed", "output", "sgm_debug"};
+
+std::string g_create_error;
+
+__global__ void k_fill(uint8_t *p, uint8_t v, size_t n) {
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct LevelPlan {
+    int w = 0, h = 0;
+    double K[9], Kinv[9];
+    int F = 0, D = 0, sumG = 0;
+    int G[kMaxFam], W[kMaxFam], foff[kMaxFam], goff[kMaxFam];
+    double inv_dmin[kMaxFam], step[kMaxFam];
+    bool windows = false, sn = false;
+    size_t h_off = 0;   // offset (doubles) of this level's homographies in the parameter blob
+    size_t d_off = 0;   // offset (doubles) of this level's plane lists
+};
+
+struct FramePlan {
+    int n_levels = 0, n_views = 0, nL = 0, nR = 0, m = 0;
+    int w = 0, h = 0;
+    int F = 0;
+    double fam_n[kMaxFam][3];
+    int p1 = 0;
+    int lut[256];
+    std::vector<double> blob;   // homographies then plane lists, all levels
+    LevelPlan lv[FASSMVS_MAX_LEVELS];
+    int side[kMaxViews];
+    double work_hyp = 0, work_hyp_views = 0, sgm_bytes = 0;
+};
+
+struct TimedEvent {
+    int stage;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct fassmvs_handle {
+    fassmvs_config cfg;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    bool latched = false;
+    std::mutex mu;
+
+    // frame state (one slot)
+    bool busy = false;
+    uint64_t ticket = 0, next_ticket = 1;
+    hipEvent_t done = nullptr;
+    FramePlan plan;
+    int out_w = 0, out_h = 0;
+
+    // device buffers
+    size_t held = 0;
+    DevBuf pyr[kMaxViews + 1];       // every level of each image, level 0 first
+    DevBuf ct, S, wta, c3, params, work_ctr;
+    DevBuf sgmbuf[8];
+    DevBuf sbar;
+    struct LevelBufs {
+        DevBuf depth_raw, depth, nraw, normal, conf, label, fam, offs, dI, dbar, nbar;
+    } lb[FASSMVS_MAX_LEVELS];
+    // pinned staging
+    void *pin = nullptr;
+    size_t pin_bytes = 0;
+
+    // timers
+    std::vector<TimedEvent> pending_timers;
+    std::vector<hipEvent_t> event_pool;
+    double stage_ms[ST_COUNT] = {};
+    int32_t stage_n[ST_COUNT] = {};
+    double last_work[4] = {};
+    unsigned long long sweep_work = 0;
+};
+
+namespace {
+
+fassmvs_status fail(fassmvs_handle *h, fassmvs_status st, const std::string &msg) {
+    if (h) h->err = msg;
+    return st;
+}
+
+fassmvs_status dev_fail(fassmvs_handle *h, hipError_t e, const char *what) {
+    h->latched = true;
+    h->err = std::string(what) + ": " + hipGetErrorString(e);
+    return FASSMVS_EDEVICE;
+}
+
+#define HIPCHK(h, expr, what)                                   \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return dev_fail((h), e_, (what)); \
+    } while (0)
+
+fassmvs_status ensure(fassmvs_handle *h, DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return FASSMVS_OK;
+    size_t want = bytes + bytes / 8;   // some headroom for the next, larger frame
+    if (h->cfg.hbm_budget_bytes && h->held - b.bytes + want > h->cfg.hbm_budget_bytes) {
+        want = bytes;
+        if (h->held - b.bytes + want > h->cfg.hbm_budget_bytes)
+            return fail(h, FASSMVS_ENOMEM, "frame exceeds the handle's HBM budget");
+    }
+    if (b.p) {
+        hipFree(b.p);
+        h->held -= b.bytes;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(h, FASSMVS_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    }
+    b.bytes = want;
+    h->held += want;
+    return FASSMVS_OK;
+}
+
+void release(DevBuf &b) {
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+hipEvent_t get_event(fassmvs_handle *h) {
+    if (!h->event_pool.empty()) {
+        hipEvent_t e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Timer {
+    fassmvs_handle *h;
+    int stage;
+    hipEvent_t a = nullptr;
+    Timer(fassmvs_handle *hh, int st) : h(hh), stage(st) {
+        if (h->cfg.profile) {
+            a = get_event(h);
+            if (a) hipEventRecord(a, h->stream);
+        }
+    }
+    ~Timer() {
+        if (a) {
+            hipEvent_t b = get_event(h);
+            if (b) {
+                hipEventRecord(b, h->stream);
+                h->pending_timers.push_back({stage, a, b});
+            } else {
+                h->event_pool.push_back(a);
+            }
+        }
+    }
+};
+
+void collect_timers(fassmvs_handle *h) {
+    for (auto &t : h->pending_timers) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            h->stage_ms[t.stage] += ms;
+            h->stage_n[t.stage] += 1;
+        }
+        h->event_pool.push_back(t.a);
+        h->event_pool.push_back(t.b);
+    }
+    h->pending_timers.clear();
+}
+
+// Sweep tile height knob (FASSMVS_SWEEP_ROWS = 4 or 8 rows per thread).
+int sweep_rows() {
+    static int v = [] {
+        const char *e = std::getenv("FASSMVS_SWEEP_ROWS");
+        return (e && std::atoi(e) == 4) ? 4 : 8;
+    }();
+    return v;
+}
+
+bool finite_all(const double *v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// ------------------------------------------------------------- geometry
+// Inverse of the upper-triangular intrinsic matrix at level l (focal
+// lengths, skew and principal point scaled by 2^-l), in closed form.
+bool kinv_level(const double *K, int level, double *Kl, double *Ki) {
+    if (K[3] != 0.0 || K[6] != 0.0 || K[7] != 0.0 || K[8] != 1.0) return false;
+    double sc = std::ldexp(1.0, -level);
+    double fx = K[0] * sc, s = K[1] * sc, cx = K[2] * sc, fy = K[4] * sc, cy = K[5] * sc;
+    if (!(fx > 0.0) || !(fy > 0.0)) return false;
+    Ki[0] = 1.0 / fx;
+    Ki[1] = -s / (fx * fy);
+    Ki[2] = (s * cy - cx * fy) / (fx * fy);
+    Ki[3] = 0.0;
+    Ki[4] = 1.0 / fy;
+    Ki[5] = -cy / fy;
+    Ki[6] = 0.0;
+    Ki[7] = 0.0;
+    Ki[8] = 1.0;
+    const double kl[9] = {fx, s, cx, 0.0, fy, cy, 0.0, 0.0, 1.0};
+    std::memcpy(Kl, kl, sizeof(kl));
+    return true;
+}
+
+// [R|t] of view k relative to the reference: R = R_k R_ref^T, t = t_k - R t_ref.
+void relative_pose(const double *Rr, const double *tr, const double *Rk, const double *tk, double *R, double *t) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += Rk[i * 3 + k] * Rr[j * 3 + k];
+            R[i * 3 + j] = s;
+        }
+    for (int i = 0; i < 3; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < 3; ++j) s += R[i * 3 + j] * tr[j];
+        t[i] = tk[i] - s;
+    }
+}
+
+// Plane-induced homography K (R - t n^T / delta) K^-1 (Eq. homography).
+void homography(const double *K, const double *Ki, const double *R, const double *t, const double *n, double delta,
+                double *H) {
+    double M[9], A[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[i * 3 + j] = R[i * 3 + j] - t[i] * n[j] / delta;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += K[i * 3 + k] * M[k * 3 + j];
+            A[i * 3 + j] = s;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += A[i * 3 + k] * Ki[k * 3 + j];
+            H[i * 3 + j] = s;
+        }
+}
+
+fassmvs_status validate_config(const fassmvs_config *c, std::string &msg) {
+    if (c->n_levels < 1 || c->n_levels > FASSMVS_MAX_LEVELS) { msg = "n_levels must be 1..5"; return FASSMVS_EINVAL; }
+    if (!(c->census_w & 1) || !(c->census_h & 1) || c->census_w < 3 || c->census_h < 3) {
+        msg = "census window must be odd";
+        return FASSMVS_EINVAL;
+    }
+    if (c->census_w * c->census_h - 1 > 64) { msg = "census window exceeds 64 bits"; return FASSMVS_EINVAL; }
+    bool ok_cw = (c->census_w == 5 && c->census_h == 5) || (c->census_w == 9 && c->census_h == 7) ||
+                 (c->census_w == 7 && c->census_h == 7) || (c->census_w == 3 && c->census_h == 3);
+    if (!ok_cw) { msg = "census window not built (3x3, 5x5, 7x7, 9x7)"; return FASSMVS_EUNSUPPORTED; }
+    if (c->n_paths != 4 && c->n_paths != 8) { msg = "n_paths must be 4 or 8"; return FASSMVS_EINVAL; }
+    if (c->sgm_variant != 0 && c->sgm_variant != 1) { msg = "sgm_variant must be 0 or 1"; return FASSMVS_EINVAL; }
+    if (c->p1 < 0 || c->p1 > 4096) { msg = "p1 out of range"; return FASSMVS_EINVAL; }
+    if (c->p2_mode != 0 && c->p2_mode != 1) { msg = "p2_mode must be 0 or 1"; return FASSMVS_EINVAL; }
+    if (c->p2_mode == 0 && (c->p2_fixed < c->p1 || c->p2_fixed > 65535)) {
+        msg = "fixed P2 must be >= P1";
+        return FASSMVS_EINVAL;
+    }
+    if (c->p2_mode == 1 && (!(c->p2_alpha >= 0.0) || !(c->p2_beta > 0.0) || !std::isfinite(c->p2_alpha))) {
+        msg = "adaptive P2 needs alpha >= 0 and beta > 0";
+        return FASSMVS_EINVAL;
+    }
+    if (c->window_labels < 0) { msg = "window_labels must be >= 0"; return FASSMVS_EINVAL; }
+    if (c->normal_radius < 1 || c->normal_radius > 4) { msg = "normal_radius must be 1..4"; return FASSMVS_EINVAL; }
+    if (!(c->normal_beta > 0.0) || !(c->conf_rho_deg > 0.0 && c->conf_rho_deg < 90.0)) {
+        msg = "normal_beta > 0 and 0 < rho < 90 required";
+        return FASSMVS_EINVAL;
+    }
+    return FASSMVS_OK;
+}
+
+// Validate a frame and build its plan (EINVAL / EUNSUPPORTED on failure).
+fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fassmvs_image *views, const int8_t *side,
+                         int n_views, const double *K, const fassmvs_plane_family *fam, int F, FramePlan &P) {
+    const fassmvs_config &c = h->cfg;
+    if (!ref || !views || !side || !K || !fam) return fail(h, FASSMVS_EINVAL, "null argument");
+    if (n_views < 1 || n_views > kMaxViews) return fail(h, FASSMVS_EINVAL, "n_views must be 1..8");
+    if (F < 1 || F > kMaxFam) return fail(h, FASSMVS_EINVAL, "n_families must be 1..8");
+    const int w = ref->width, hh = ref->height;
+    if (w <= 0 || hh <= 0 || ref->stride < w || !ref->pixels) return fail(h, FASSMVS_EINVAL, "bad reference image");
+    if ((w >> (c.n_levels - 1)) < 8 || (hh >> (c.n_levels - 1)) < 8)
+        return fail(h, FASSMVS_EINVAL, "image too small for the pyramid height");
+    if ((size_t)w * hh > (size_t)1 << 28) return fail(h, FASSMVS_EINVAL, "image too large");
+    if (!finite_all(ref->R, 9) || !finite_all(ref->t, 3)) return fail(h, FASSMVS_EINVAL, "non-finite reference pose");
+    P = FramePlan();
+    P.n_levels = c.n_levels;
+    P.n_views = n_views;
+    P.w = w;
+    P.h = hh;
+    P.F = F;
+    for (int k = 0; k < n_views; ++k) {
+        const fassmvs_image &v = views[k];
+        if (v.width != w || v.height != hh || v.stride < w || !v.pixels)
+            return fail(h, FASSMVS_EINVAL, "matching images must have the reference's size");
+        if (!finite_all(v.R, 9) || !finite_all(v.t, 3)) return fail(h, FASSMVS_EINVAL, "non-finite view pose");
+        if (side[k] == -1) P.nL++;
+        else if (side[k] == 1) P.nR++;
+        else return fail(h, FASSMVS_EINVAL, "view_side must be -1 or +1");
+        P.side[k] = side[k];
+    }
+    P.m = std::max(P.nL, P.nR);
+    const int nbits = c.census_w * c.census_h - 1;
+    if (P.m * nbits > 255) return fail(h, FASSMVS_EUNSUPPORTED, "matching cost exceeds 8 bits (m * census bits > 255)");
+    if (!(std::fabs(K[0]) > 0) || K[3] != 0.0 || K[6] != 0.0 || K[7] != 0.0 || K[8] != 1.0 || !finite_all(K, 9))
+        return fail(h, FASSMVS_EINVAL, "K must be upper triangular with K[8] = 1");
+    // relative poses and camera centres in reference coordinates
+    double Rrel[kMaxViews][9], trel[kMaxViews][3];
+    for (int k = 0; k < n_views; ++k) relative_pose(ref->R, ref->t, views[k].R, views[k].t, Rrel[k], trel[k]);
+    for (int f = 0; f < F; ++f) {
+        const fassmvs_plane_family &pf = fam[f];
+        double nn = pf.n[0] * pf.n[0] + pf.n[1] * pf.n[1] + pf.n[2] * pf.n[2];
+        if (!finite_all(pf.n, 3) || std::fabs(nn - 1.0) > 1e-6 || !(pf.n[2] < 0.0))
+            return fail(h, FASSMVS_EINVAL, "plane normals must be unit vectors facing the camera");
+        if (!(pf.delta_min > 0.0) || !(pf.delta_max > pf.delta_min) || !std::isfinite(pf.delta_max))
+            return fail(h, FASSMVS_EINVAL, "plane distances need 0 < delta_min < delta_max");
+        if (pf.count < 2 || pf.count > FASSMVS_MAX_TOP_PLANES)
+            return fail(h, FASSMVS_EINVAL, "plane count at the coarsest level must be 2..256");
+        for (int i = 0; i < 3; ++i) P.fam_n[f][i] = pf.n[i];
+        // every camera centre in front of the nearest plane
+        for (int k = 0; k < n_views; ++k) {
+            double C[3];
+            for (int i = 0; i < 3; ++i)
+                C[i] = -(Rrel[k][0 * 3 + i] * trel[k][0] + Rrel[k][1 * 3 + i] * trel[k][1] + Rrel[k][2 * 3 + i] * trel[k][2]);
+            if (!(pf.n[0] * C[0] + pf.n[1] * C[1] + pf.n[2] * C[2] + pf.delta_min > 0.0))
+                return fail(h, FASSMVS_EINVAL, "a camera centre lies behind the nearest sweep plane");
+        }
+    }
+    // penalties: P1 and P2 scaled by the subset size m
+    P.p1 = P.m * c.p1;
+    int p2max = 0;
+    for (int i = 0; i < 256; ++i) {
+        if (c.p2_mode == 0)
+            P.lut[i] = P.m * c.p2_fixed;
+        else
+            P.lut[i] = (int)std::floor((double)P.p1 * (1.0 + c.p2_alpha * std::exp(-(double)i / c.p2_beta)) + 0.5);
+        p2max = std::max(p2max, P.lut[i]);
+    }
+    if ((long)c.n_paths * ((long)P.m * nbits + p2max) > 65535)
+        return fail(h, FASSMVS_EUNSUPPORTED, "aggregated cost could exceed 16 bits; lower P1/P2 or views");
+    // levels
+    size_t hsz = 0, dsz = 0;
+    for (int l = 0; l < c.n_levels; ++l) {
+        LevelPlan &L = P.lv[l];
+        L.w = l == 0 ? w : P.lv[l - 1].w / 2;
+        L.h = l == 0 ? hh : P.lv[l - 1].h / 2;
+        if (!kinv_level(K, l, L.K, L.Kinv)) return fail(h, FASSMVS_EINVAL, "K must have positive focal lengths");
+        L.F = F;
+        const bool top = l == c.n_levels - 1;
+        L.windows = !top && c.window_labels > 0;
+        L.sn = !top && c.sgm_variant == 1;
+        int D = 0, sumG = 0;
+        for (int f = 0; f < F; ++f) {
+            long G = (long)fam[f].count << (c.n_levels - 1 - l);
+            if (G > 65535) return fail(h, FASSMVS_EUNSUPPORTED, "plane list too long");
+            L.G[f] = (int)G;
+            L.W[f] = L.windows ? std::min(c.window_labels, L.G[f]) : L.G[f];
+            L.foff[f] = D;
+            L.goff[f] = sumG;
+            D += L.W[f];
+            sumG += L.G[f];
+            L.inv_dmin[f] = 1.0 / fam[f].delta_min;
+            L.step[f] = (L.inv_dmin[f] - 1.0 / fam[f].delta_max) / (double)(L.G[f] - 1);
+        }
+        if (D > FASSMVS_MAX_LABELS) return fail(h, FASSMVS_EUNSUPPORTED, "more than 512 labels per pixel at a level");
+        L.D = D;
+        L.sumG = sumG;
+        L.h_off = hsz;
+        hsz += (size_t)n_views * sumG * 9;
+        P.work_hyp += (double)L.w * L.h * D;
+        P.work_hyp_views += (double)L.w * L.h * D * n_views;
+        // S read once per path, each path's u16 costs written once and read once
+        P.sgm_bytes += (double)L.w * L.h * D * (c.n_paths * (1.0 + 2.0 + 2.0));
+    }
+    for (int l = 0; l < c.n_levels; ++l) {
+        P.lv[l].d_off = hsz + dsz;
+        dsz += P.lv[l].sumG;
+    }
+    P.blob.assign(hsz + dsz, 0.0);
+    for (int l = 0; l < c.n_levels; ++l) {
+        LevelPlan &L = P.lv[l];
+        double *dl = P.blob.data() + L.d_off;
+        for (int f = 0; f < F; ++f) {
+            double a = L.inv_dmin[f];
+            for (int j = 0; j < L.G[f]; ++j) dl[L.goff[f] + j] = 1.0 / (a - (double)j * L.step[f]);
+        }
+        for (int k = 0; k < n_views; ++k)
+            for (int f = 0; f < F; ++f)
+                for (int j = 0; j < L.G[f]; ++j) {
+                    double *H = P.blob.data() + L.h_off + ((size_t)k * L.sumG + L.goff[f] + j) * 9;
+                    homography(L.K, L.Kinv, Rrel[k], trel[k], P.fam_n[f], dl[L.goff[f] + j], H);
+                    if (!finite_all(H, 9)) return fail(h, FASSMVS_EINVAL, "degenerate homography");
+                }
+    }
+    return FASSMVS_OK;
+}
+
+size_t pyr_total(int w, int hh, int levels) {
+    size_t s = 0;
+    for (int l = 0; l < levels; ++l) {
+        s += (size_t)w * hh;
+        w /= 2;
+        hh /= 2;
+    }
+    return s;
+}
+
+fassmvs_status alloc_frame(fassmvs_handle *h, const FramePlan &P) {
+    const fassmvs_config &c = h->cfg;
+    const size_t N0 = (size_t)P.w * P.h;
+    size_t Dmax = 0, NDmax = 0;
+    for (int l = 0; l < P.n_levels; ++l) {
+        Dmax = std::max(Dmax, (size_t)P.lv[l].D);
+        NDmax = std::max(NDmax, (size_t)P.lv[l].w * P.lv[l].h * P.lv[l].D);
+    }
+    fassmvs_status st;
+    size_t pyr = pyr_total(P.w, P.h, P.n_levels);
+    for (int i = 0; i <= P.n_views; ++i)
+        if ((st = ensure(h, h->pyr[i], pyr)) != FASSMVS_OK) return st;
+    if ((st = ensure(h, h->ct, N0 * 8)) != FASSMVS_OK) return st;
+    if ((st = ensure(h, h->S, NDmax)) != FASSMVS_OK) return st;
+    for (int i = 0; i < c.n_paths; ++i)
+        if ((st = ensure(h, h->sgmbuf[i], NDmax * 2)) != FASSMVS_OK) return st;
+    if (c.sgm_debug && (st = ensure(h, h->sbar, NDmax * 2)) != FASSMVS_OK) return st;
+    if ((st = ensure(h, h->wta, N0 * 2)) != FASSMVS_OK) return st;
+    if ((st = ensure(h, h->c3, N0 * 6)) != FASSMVS_OK) return st;
+    if ((st = ensure(h, h->params, P.blob.size() * 8)) != FASSMVS_OK) return st;
+    if ((st = ensure(h, h->work_ctr, 8)) != FASSMVS_OK) return st;
+    for (int l = 0; l < P.n_levels; ++l) {
+        size_t N = (size_t)P.lv[l].w * P.lv[l].h;
+        auto &B = h->lb[l];
+        if ((st = ensure(h, B.depth_raw, N * 4)) || (st = ensure(h, B.depth, N * 4)) ||
+            (st = ensure(h, B.nraw, N * 12)) || (st = ensure(h, B.normal, N * 12)) || (st = ensure(h, B.conf, N * 4)) ||
+            (st = ensure(h, B.label, N * 4)) || (st = ensure(h, B.fam, N * 4)) ||
+            (st = ensure(h, B.offs, N * 4 * P.F)) || (st = ensure(h, B.dI, N * 8 * P.F)) ||
+            (st = ensure(h, B.dbar, N * 4)) || (st = ensure(h, B.nbar, N * 12)))
+            return st;
+    }
+    size_t pin = pyr_total(P.w, P.h, 1) * (P.n_views + 1) + P.blob.size() * 8 + 64;
+    if (h->pin_bytes < pin) {
+        if (h->pin) hipHostFree(h->pin);
+        h->pin = nullptr;
+        h->pin_bytes = 0;
+        if (hipHostMalloc(&h->pin, pin) != hipSuccess) {
+            (void)hipGetLastError();
+            h->pin = nullptr;
+            return fail(h, FASSMVS_ENOMEM, "pinned staging allocation failed");
+        }
+        h->pin_bytes = pin;
+    }
+    return FASSMVS_OK;
+}
+
+// Run the SGM stage of one level: every direction writes its own path-cost
+// buffer in one launch (all paths of all directions concurrently), then a
+// streaming kernel sums the buffers and takes the argmin.  With Sbar the
+// full aggregate is also written (tests).
+fassmvs_status run_sgm(fassmvs_handle *h, const LevelPlan &L, const uint8_t *S, const int32_t *offs,
+                       const int8_t *dI, const uint8_t *ref, int p1, const int *lut, int n_paths, uint16_t *const *bufs,
+                       uint16_t *Sbar, uint16_t *wta, uint16_t *c3) {
+    SgmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.w = L.w;
+    a.h = L.h;
+    a.D = L.D;
+    a.n_fam = L.F;
+    for (int f = 0; f < L.F; ++f) {
+        a.W[f] = L.W[f];
+        a.foff[f] = L.foff[f];
+    }
+    a.S = S;
+    a.offs = offs;
+    a.dI = dI;
+    a.ref = ref;
+    a.p1 = p1;
+    for (int i = 0; i < 256; ++i) a.lut[i] = lut[i];
+    {
+        Timer t(h, ST_SGM_DIRS);
+        a.n_dirs = n_paths;
+        for (int d = 0; d < n_paths; ++d) {
+            a.dirs[d] = d;
+            a.out[d] = bufs[d];
+        }
+        HIPCHK(h, launch_sgm(a, h->stream), "sgm launch");
+    }
+    if (Sbar) {
+        Timer t(h, ST_SGM_DEBUG);
+        HIPCHK(h, launch_sum_u16(bufs, n_paths, (size_t)L.w * L.h * L.D, Sbar, h->stream), "sum launch");
+    }
+    if (wta) {
+        Timer t(h, ST_SGM_WTA);
+        a.n_dirs = 0;
+        a.n_in = n_paths;
+        for (int b = 0; b < n_paths; ++b) a.in[b] = bufs[b];
+        a.final_mode = 1;
+        a.wta = wta;
+        a.c3 = c3;
+        HIPCHK(h, launch_sgm(a, h->stream), "wta launch");
+    }
+    return FASSMVS_OK;
+}
+
+fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
+    const fassmvs_config &c = h->cfg;
+    double *dblob = (double *)h->params.p;
+    {
+        Timer t(h, ST_PYR);
+        for (int i = 0; i <= P.n_views; ++i) {
+            uint8_t *base = (uint8_t *)h->pyr[i].p;
+            size_t off = 0;
+            for (int l = 0; l + 1 < P.n_levels; ++l) {
+                const LevelPlan &L = P.lv[l];
+                HIPCHK(h, launch_pyr_down(base + off, L.w, L.h, L.w, base + off + (size_t)L.w * L.h, h->stream),
+                       "pyramid launch");
+                off += (size_t)L.w * L.h;
+            }
+        }
+    }
+    h->sweep_work = 0;
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, h->stream, (uint8_t *)h->work_ctr.p, (uint8_t)0, (size_t)8);
+    HIPCHK(h, hipGetLastError(), "work counter");
+    size_t lvl_off[FASSMVS_MAX_LEVELS];
+    {
+        size_t off = 0;
+        for (int l = 0; l < P.n_levels; ++l) {
+            lvl_off[l] = off;
+            off += (size_t)P.lv[l].w * P.lv[l].h;
+        }
+    }
+    for (int l = P.n_levels - 1; l >= 0; --l) {
+        const LevelPlan &L = P.lv[l];
+        const size_t N = (size_t)L.w * L.h;
+        auto &B = h->lb[l];
+        const uint8_t *ref = (const uint8_t *)h->pyr[0].p + lvl_off[l];
+        {
+            Timer t(h, ST_CENSUS);
+            HIPCHK(h, launch_census(ref, L.w, L.h, c.census_w, c.census_h, (uint64_t *)h->ct.p, h->stream), "census");
+        }
+        const int32_t *offs = L.windows ? (const int32_t *)B.offs.p : nullptr;
+        const int8_t *dI = L.sn ? (const int8_t *)B.dI.p : nullptr;
+        {
+            Timer t(h, ST_SWEEP);
+            SweepArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.w = L.w;
+            a.h = L.h;
+            a.cw = c.census_w;
+            a.ch = c.census_h;
+            a.n_views = P.n_views;
+            a.nL = P.nL;
+            a.nR = P.nR;
+            a.m = P.m;
+            for (int k = 0; k < P.n_views; ++k) {
+                a.views[k] = (const uint8_t *)h->pyr[k + 1].p + lvl_off[l];
+                a.side[k] = P.side[k];
+            }
+            a.ct_ref = (const uint64_t *)h->ct.p;
+            a.n_fam = L.F;
+            a.D = L.D;
+            a.sumG = L.sumG;
+            for (int f = 0; f < L.F; ++f) {
+                a.G[f] = L.G[f];
+                a.W[f] = L.W[f];
+                a.foff[f] = L.foff[f];
+                a.goff[f] = L.goff[f];
+            }
+            a.H = dblob + L.h_off;
+            a.offs = offs;
+            a.S = (uint8_t *)h->S.p;
+            a.work = (unsigned long long *)h->work_ctr.p;
+            a.rows_per_thread = sweep_rows();
+            HIPCHK(h, launch_sweep(a, h->stream), "sweep launch");
+        }
+        uint16_t *bufs[8];
+        for (int i = 0; i < 8; ++i) bufs[i] = (uint16_t *)h->sgmbuf[i].p;
+        fassmvs_status st = run_sgm(h, L, (const uint8_t *)h->S.p, offs, dI, ref, P.p1, P.lut, c.n_paths, bufs,
+                                    c.sgm_debug ? (uint16_t *)h->sbar.p : nullptr, (uint16_t *)h->wta.p,
+                                    (uint16_t *)h->c3.p);
+        if (st != FASSMVS_OK) return st;
+        {
+            Timer t(h, ST_REFINE);
+            RefineArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.w = L.w;
+            a.h = L.h;
+            a.n_fam = L.F;
+            for (int f = 0; f < L.F; ++f) {
+                a.W[f] = L.W[f];
+                a.G[f] = L.G[f];
+                a.foff[f] = L.foff[f];
+                a.goff[f] = L.goff[f];
+                for (int i = 0; i < 3; ++i) a.fam_n[f][i] = P.fam_n[f][i];
+            }
+            std::memcpy(a.Kinv, L.Kinv, sizeof(a.Kinv));
+            a.delta = dblob + L.d_off;
+            a.offs = offs;
+            a.wta = (const uint16_t *)h->wta.p;
+            a.c3 = (const uint16_t *)h->c3.p;
+            a.label = (int32_t *)B.label.p;
+            a.fam = (int32_t *)B.fam.p;
+            a.depth = (float *)(c.median ? B.depth_raw.p : B.depth.p);
+            HIPCHK(h, launch_refine(a, h->stream), "refine launch");
+        }
+        if (c.median) {
+            Timer t(h, ST_MEDIAN);
+            HIPCHK(h, launch_median5((const float *)B.depth_raw.p, L.w, L.h, (float *)B.depth.p, h->stream), "median");
+        }
+        {
+            Timer t(h, ST_NORMALS);
+            NormalArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.w = L.w;
+            a.h = L.h;
+            a.radius = c.normal_radius;
+            a.beta = c.normal_beta;
+            a.cos_rho = std::cos(c.conf_rho_deg * 3.14159265358979323846 / 180.0);
+            std::memcpy(a.Kinv, L.Kinv, sizeof(a.Kinv));
+            a.n_fam = L.F;
+            for (int f = 0; f < L.F; ++f)
+                for (int i = 0; i < 3; ++i) a.fam_n[f][i] = P.fam_n[f][i];
+            a.depth = (const float *)B.depth.p;
+            a.img = ref;
+            a.label = (const int32_t *)B.label.p;
+            a.fam = (const int32_t *)B.fam.p;
+            a.nraw = (float *)B.nraw.p;
+            a.normal = (float *)B.normal.p;
+            a.conf = (float *)B.conf.p;
+            HIPCHK(h, launch_normals(a, h->stream), "normals launch");
+        }
+        if (l > 0) {
+            Timer t(h, ST_SEED);
+            const LevelPlan &Lf = P.lv[l - 1];
+            auto &Bf = h->lb[l - 1];
+            SeedArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.cw = L.w;
+            a.ch = L.h;
+            a.fw = Lf.w;
+            a.fh = Lf.h;
+            a.n_fam = Lf.F;
+            std::memcpy(a.Kinv, Lf.Kinv, sizeof(a.Kinv));
+            for (int f = 0; f < Lf.F; ++f) {
+                for (int i = 0; i < 3; ++i) a.fam_n[f][i] = P.fam_n[f][i];
+                a.inv_dmin[f] = Lf.inv_dmin[f];
+                a.step[f] = Lf.step[f];
+                a.G[f] = Lf.G[f];
+                a.W[f] = Lf.W[f];
+            }
+            a.depth_c = (const float *)B.depth.p;
+            a.normal_c = (const float *)B.normal.p;
+            a.dbar = (float *)Bf.dbar.p;
+            a.nbar = (float *)Bf.nbar.p;
+            a.offs = (int32_t *)Bf.offs.p;
+            a.dI = Lf.sn ? (int8_t *)Bf.dI.p : nullptr;
+            HIPCHK(h, launch_seed(a, h->stream), "seed launch");
+        }
+        (void)N;
+    }
+    return FASSMVS_OK;
+}
+
+fassmvs_status copy_out(fassmvs_handle *h, void *dst, const void *src, size_t bytes, int mem_kind) {
+    if (!dst) return FASSMVS_OK;
+    hipMemcpyKind k = mem_kind == FASSMVS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(h, hipMemcpyAsync(dst, src, bytes, k, h->stream), "output copy");
+    return FASSMVS_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+void fassmvs_config_default(fassmvs_config *c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->n_levels = 3;
+    c->census_w = 9;
+    c->census_h = 7;
+    c->n_paths = 8;
+    c->sgm_variant = 0;
+    c->p1 = 24;
+    c->p2_mode = 1;
+    c->p2_fixed = 64;
+    c->p2_alpha = 8.0;
+    c->p2_beta = 10.0;
+    c->window_labels = 128;
+    c->median = 1;
+    c->normal_radius = 2;
+    c->normal_beta = 10.0;
+    c->conf_rho_deg = 60.0;
+}
+
+fassmvs_status fassmvs_create(const fassmvs_config *cfg, fassmvs_handle **out) {
+    if (!out) return FASSMVS_EINVAL;
+    *out = nullptr;
+    if (!cfg) {
+        g_create_error = "null config";
+        return FASSMVS_EINVAL;
+    }
+    std::string msg;
+    fassmvs_status st = validate_config(cfg, msg);
+    if (st != FASSMVS_OK) {
+        g_create_error = msg;
+        return st;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        g_create_error = "no HIP device";
+        return FASSMVS_EDEVICE;
+    }
+    if (cfg->device < 0 || cfg->device >= ndev) {
+        g_create_error = "device ordinal out of range";
+        return FASSMVS_EINVAL;
+    }
+    if (hipSetDevice(cfg->device) != hipSuccess) {
+        g_create_error = "hipSetDevice failed";
+        return FASSMVS_EDEVICE;
+    }
+    fassmvs_handle *h = new fassmvs_handle();
+    h->cfg = *cfg;
+    if (cfg->stream) {
+        h->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete h;
+            g_create_error = "stream creation failed";
+            return FASSMVS_EDEVICE;
+        }
+        h->own_stream = true;
+    }
+    if (hipEventCreateWithFlags(&h->done, hipEventDisableTiming) != hipSuccess) {
+        if (h->own_stream) hipStreamDestroy(h->stream);
+        delete h;
+        g_create_error = "event creation failed";
+        return FASSMVS_EDEVICE;
+    }
+    *out = h;
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref, const fassmvs_image *views,
+                                    const int8_t *view_side, int32_t n_views, const double K[9],
+                                    const fassmvs_plane_family *families, int32_t n_families, int32_t mem_kind,
+                                    uint64_t *ticket) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (h->latched) return FASSMVS_EDEVICE;
+    if (h->busy) return fail(h, FASSMVS_EBUSY, "a frame is in flight; poll it first");
+    if (!ticket) return fail(h, FASSMVS_EINVAL, "null ticket");
+    if (mem_kind != FASSMVS_MEM_HOST && mem_kind != FASSMVS_MEM_DEVICE) return fail(h, FASSMVS_EINVAL, "bad mem_kind");
+    HIPCHK(h, hipSetDevice(h->cfg.device), "hipSetDevice");
+    FramePlan &P = h->plan;
+    fassmvs_status st = make_plan(h, ref, views, view_side, n_views, K, families, n_families, P);
+    if (st != FASSMVS_OK) return st;
+    if ((st = alloc_frame(h, P)) != FASSMVS_OK) return st;
+    const size_t N0 = (size_t)P.w * P.h;
+    {
+        Timer t(h, ST_UPLOAD);
+        // images -> level 0 of each pyramid
+        uint8_t *pin = (uint8_t *)h->pin;
+        for (int i = 0; i <= P.n_views; ++i) {
+            const fassmvs_image &im = i == 0 ? *ref : views[i - 1];
+            uint8_t *dst = (uint8_t *)h->pyr[i].p;
+            if (mem_kind == FASSMVS_MEM_HOST) {
+                uint8_t *stg = pin + N0 * i;
+                for (int y = 0; y < P.h; ++y) std::memcpy(stg + (size_t)y * P.w, im.pixels + (size_t)y * im.stride, P.w);
+                HIPCHK(h, hipMemcpyAsync(dst, stg, N0, hipMemcpyHostToDevice, h->stream), "image upload");
+            } else {
+                HIPCHK(h, hipMemcpy2DAsync(dst, P.w, im.pixels, im.stride, P.w, P.h, hipMemcpyDeviceToDevice, h->stream),
+                       "image copy");
+            }
+        }
+        double *pb = (double *)(pin + N0 * (P.n_views + 1) + 64 - ((uintptr_t)(pin + N0 * (P.n_views + 1)) & 63));
+        std::memcpy(pb, P.blob.data(), P.blob.size() * 8);
+        HIPCHK(h, hipMemcpyAsync(h->params.p, pb, P.blob.size() * 8, hipMemcpyHostToDevice, h->stream), "params");
+    }
+    if ((st = enqueue_frame(h, P)) != FASSMVS_OK) return st;
+    HIPCHK(h, hipMemcpyAsync(&h->sweep_work, h->work_ctr.p, 8, hipMemcpyDeviceToHost, h->stream), "work counter");
+    HIPCHK(h, hipEventRecord(h->done, h->stream), "event record");
+    h->out_w = P.w;
+    h->out_h = P.h;
+    h->busy = true;
+    h->ticket = h->next_ticket++;
+    *ticket = h->ticket;
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_poll(fassmvs_handle *h, uint64_t ticket, float *depth, float *normal, float *confidence,
+                            int32_t mem_kind, int32_t wait_ms) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (h->latched) return FASSMVS_EDEVICE;
+    if (!h->busy || ticket != h->ticket) return fail(h, FASSMVS_ENOTFOUND, "unknown ticket");
+    if (mem_kind != FASSMVS_MEM_HOST && mem_kind != FASSMVS_MEM_DEVICE) return fail(h, FASSMVS_EINVAL, "bad mem_kind");
+    HIPCHK(h, hipSetDevice(h->cfg.device), "hipSetDevice");
+    auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        hipError_t e = hipEventQuery(h->done);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) return dev_fail(h, e, "frame execution");
+        if (wait_ms == 0) return FASSMVS_PENDING;
+        if (wait_ms < 0) {
+            HIPCHK(h, hipEventSynchronize(h->done), "frame execution");
+            break;
+        }
+        double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (el >= wait_ms) return FASSMVS_PENDING;
+        std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
+    const size_t N0 = (size_t)h->out_w * h->out_h;
+    auto &B = h->lb[0];
+    fassmvs_status st;
+    {
+        Timer t(h, ST_OUTPUT);
+        if ((st = copy_out(h, depth, B.depth.p, N0 * 4, mem_kind)) != FASSMVS_OK) return st;
+        if ((st = copy_out(h, normal, B.normal.p, N0 * 12, mem_kind)) != FASSMVS_OK) return st;
+        if ((st = copy_out(h, confidence, B.conf.p, N0 * 4, mem_kind)) != FASSMVS_OK) return st;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream), "output copy");
+    collect_timers(h);
+    h->last_work[0] = h->plan.work_hyp;
+    h->last_work[1] = h->plan.work_hyp_views;
+    h->last_work[2] = (double)h->sweep_work;
+    h->last_work[3] = h->plan.sgm_bytes;
+    h->busy = false;
+    return FASSMVS_OK;
+}
+
+void fassmvs_destroy(fassmvs_handle *h) {
+    if (!h) return;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        hipSetDevice(h->cfg.device);
+        hipStreamSynchronize(h->stream);
+        for (auto &b : h->pyr) release(b);
+        release(h->ct);
+        release(h->S);
+        release(h->wta);
+        release(h->c3);
+        release(h->params);
+        release(h->work_ctr);
+        release(h->sbar);
+        for (auto &b : h->sgmbuf) release(b);
+        for (auto &L : h->lb) {
+            release(L.depth_raw); release(L.depth); release(L.nraw); release(L.normal); release(L.conf);
+            release(L.label); release(L.fam); release(L.offs); release(L.dI); release(L.dbar); release(L.nbar);
+        }
+        if (h->pin) hipHostFree(h->pin);
+        for (auto &t : h->pending_timers) {
+            hipEventDestroy(t.a);
+            hipEventDestroy(t.b);
+        }
+        for (auto e : h->event_pool) hipEventDestroy(e);
+        if (h->done) hipEventDestroy(h->done);
+        if (h->own_stream) hipStreamDestroy(h->stream);
+    }
+    delete h;
+}
+
+const char *fassmvs_last_error(const fassmvs_handle *h) {
+    if (!h) return g_create_error.c_str();
+    return h->err.c_str();
+}
+
+fassmvs_status fassmvs_stage_times(fassmvs_handle *h, double *ms, int32_t *counts, int32_t n) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    for (int i = 0; i < n && i < ST_COUNT; ++i) {
+        if (ms) ms[i] = h->stage_ms[i];
+        if (counts) counts[i] = h->stage_n[i];
+    }
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_reset_stage_times(fassmvs_handle *h) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    for (int i = 0; i < ST_COUNT; ++i) {
+        h->stage_ms[i] = 0;
+        h->stage_n[i] = 0;
+    }
+    return FASSMVS_OK;
+}
+
+const char *fassmvs_stage_name(int32_t s) { return (s >= 0 && s < ST_COUNT) ? kStageNames[s] : ""; }
+
+fassmvs_status fassmvs_frame_work(fassmvs_handle *h, double *out, int32_t n) {
+    if (!h || !out) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    for (int i = 0; i < n && i < 4; ++i) out[i] = h->last_work[i];
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_level_map(fassmvs_handle *h, int32_t level, int32_t what, void *dst, size_t dst_bytes) {
+    if (!h || !dst) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    const FramePlan &P = h->plan;
+    if (level < 0 || level >= P.n_levels) return fail(h, FASSMVS_EINVAL, "no such level");
+    if (h->busy) return fail(h, FASSMVS_EBUSY, "frame in flight");
+    const LevelPlan &L = P.lv[level];
+    const size_t N = (size_t)L.w * L.h;
+    if (what == 8) {
+        if (dst_bytes < 8) return FASSMVS_EINVAL;
+        int32_t *o = (int32_t *)dst;
+        o[0] = L.w;
+        o[1] = L.h;
+        return FASSMVS_OK;
+    }
+    auto &B = h->lb[level];
+    const void *src = nullptr;
+    size_t bytes = 0;
+    switch (what) {
+        case 0: src = B.depth.p; bytes = N * 4; break;
+        case 1: src = h->cfg.median ? B.depth_raw.p : B.depth.p; bytes = N * 4; break;
+        case 2: src = B.normal.p; bytes = N * 12; break;
+        case 3: src = B.conf.p; bytes = N * 4; break;
+        case 4: src = B.label.p; bytes = N * 4; break;
+        case 5: src = B.fam.p; bytes = N * 4; break;
+        case 6: src = B.offs.p; bytes = N * 4 * P.F; break;
+        case 7: src = B.dI.p; bytes = N * 8 * P.F; break;
+        case 9:
+            if (level != 0) return fail(h, FASSMVS_EINVAL, "the cost volume is kept for level 0 only");
+            src = h->S.p;
+            bytes = N * L.D;
+            break;
+        case 20:
+            if (level != 0) return fail(h, FASSMVS_EINVAL, "the reference census is kept for level 0 only");
+            src = h->ct.p;
+            bytes = N * 8;
+            break;
+        default:
+            if (what >= 10 && what < 10 + h->cfg.n_paths && level == 0) {
+                // path costs of direction r (each direction has its own buffer)
+                src = h->sgmbuf[what - 10].p;
+                bytes = N * L.D * 2;
+                break;
+            }
+            if (what >= 30 && what <= 30 + P.n_views) {
+                size_t off = 0;
+                for (int l = 0; l < level; ++l) off += (size_t)P.lv[l].w * P.lv[l].h;
+                src = (const uint8_t *)h->pyr[what - 30].p + off;
+                bytes = N;
+                break;
+            }
+            return fail(h, FASSMVS_EINVAL, "unknown map");
+    }
+    if (dst_bytes < bytes) return fail(h, FASSMVS_EINVAL, "destination too small");
+    HIPCHK(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream), "level map copy");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "level map copy");
+    return FASSMVS_OK;
+}
+
+// ---------------------------------------------------------------- plumbing
+
+fassmvs_status fassmvs_device_alloc(fassmvs_handle *h, size_t bytes, void **ptr) {
+    if (!h || !ptr) return FASSMVS_EINVAL;
+    *ptr = nullptr;
+    hipSetDevice(h->cfg.device);
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *ptr = nullptr;
+        return fail(h, FASSMVS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_device_free(fassmvs_handle *h, void *ptr) {
+    if (!h) return FASSMVS_EINVAL;
+    if (!ptr) return FASSMVS_OK;
+    std::lock_guard<std::mutex> lk(h->mu);
+    hipSetDevice(h->cfg.device);
+    HIPCHK(h, hipStreamSynchronize(h->stream), "sync before free");
+    HIPCHK(h, hipFree(ptr), "hipFree");
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_memcpy(fassmvs_handle *h, void *dst, const void *src, size_t bytes, int32_t kind) {
+    if (!h || (!dst && bytes) || (!src && bytes)) return FASSMVS_EINVAL;
+    if (kind < 0 || kind > 2) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    hipSetDevice(h->cfg.device);
+    if (bytes == 0) return FASSMVS_OK;
+    const hipMemcpyKind k[3] = {hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice};
+    HIPCHK(h, hipStreamSynchronize(h->stream), "sync before copy");
+    HIPCHK(h, hipMemcpyAsync(dst, src, bytes, k[kind], h->stream), "copy");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "copy");
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_fill(fassmvs_handle *h, void *dst, uint8_t value, size_t bytes) {
+    if (!h || (!dst && bytes)) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    hipSetDevice(h->cfg.device);
+    if (bytes == 0) return FASSMVS_OK;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((bytes + 255) / 256)), dim3(256), 0, h->stream, (uint8_t *)dst, value,
+                       bytes);
+    HIPCHK(h, hipGetLastError(), "fill launch");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "fill");
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_synchronize(fassmvs_handle *h) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    hipSetDevice(h->cfg.device);
+    HIPCHK(h, hipStreamSynchronize(h->stream), "synchronize");
+    return FASSMVS_OK;
+}
+
+// ---------------------------------------------------------------- stage entry points
+
+#define STAGE_BEGIN                                  \
+    if (!h) return FASSMVS_EINVAL;                   \
+    std::lock_guard<std::mutex> lk(h->mu);           \
+    if (h->latched) return FASSMVS_EDEVICE;          \
+    HIPCHK(h, hipSetDevice(h->cfg.device), "hipSetDevice")
+
+#define STAGE_END                                                     \
+    HIPCHK(h, hipStreamSynchronize(h->stream), "stage execution");   \
+    return FASSMVS_OK
+
+fassmvs_status fassmvs_stage_pyr_down(fassmvs_handle *h, const uint8_t *src, int32_t w, int32_t hgt, uint8_t *dst) {
+    STAGE_BEGIN;
+    if (!src || !dst || w < 2 || hgt < 2) return fail(h, FASSMVS_EINVAL, "bad pyramid arguments");
+    HIPCHK(h, launch_pyr_down(src, w, hgt, w, dst, h->stream), "pyramid launch");
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_stage_census(fassmvs_handle *h, const uint8_t *img, int32_t w, int32_t hgt, int32_t cw,
+                                    int32_t ch, uint64_t *out) {
+    STAGE_BEGIN;
+    if (!img || !out || w < 1 || hgt < 1 || !(cw & 1) || !(ch & 1) || cw * ch - 1 > 64)
+        return fail(h, FASSMVS_EINVAL, "bad census arguments");
+    HIPCHK(h, launch_census(img, w, hgt, cw, ch, out, h->stream), "census launch");
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_stage_warp(fassmvs_handle *h, const uint8_t *src, int32_t sw, int32_t sh, const double H[9],
+                                  int32_t rw, int32_t rh, float *out) {
+    STAGE_BEGIN;
+    if (!src || !H || !out || sw < 1 || sh < 1 || rw < 1 || rh < 1) return fail(h, FASSMVS_EINVAL, "bad warp arguments");
+    if (!finite_all(H, 9)) return fail(h, FASSMVS_EINVAL, "non-finite homography");
+    fassmvs_status st = ensure(h, h->params, 9 * 8);
+    if (st != FASSMVS_OK) return st;
+    HIPCHK(h, hipMemcpyAsync(h->params.p, H, 72, hipMemcpyHostToDevice, h->stream), "H upload");
+    HIPCHK(h, launch_warp(src, sw, sh, (const double *)h->params.p, rw, rh, out, h->stream), "warp launch");
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_stage_cost(fassmvs_handle *h, int32_t w, int32_t hgt, const uint64_t *ct_ref, int32_t n_views,
+                                  const uint8_t *const *views, const int8_t *view_side, int32_t cw, int32_t ch,
+                                  int32_t n_fam, const int32_t *G, const int32_t *W, const double *H,
+                                  const int32_t *offs, const float *warped, uint8_t *S) {
+    STAGE_BEGIN;
+    if (!ct_ref || !views || !view_side || !G || !W || !H || !S || w < 1 || hgt < 1)
+        return fail(h, FASSMVS_EINVAL, "bad cost arguments");
+    if (n_views < 1 || n_views > kMaxViews || n_fam < 1 || n_fam > kMaxFam) return fail(h, FASSMVS_EINVAL, "bad counts");
+    SweepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.w = w;
+    a.h = hgt;
+    a.cw = cw;
+    a.ch = ch;
+    a.n_views = n_views;
+    for (int k = 0; k < n_views; ++k) {
+        if (!views[k] && !warped) return fail(h, FASSMVS_EINVAL, "null view");
+        a.views[k] = views[k];
+        a.side[k] = view_side[k];
+        if (view_side[k] < 0) a.nL++; else a.nR++;
+    }
+    a.m = std::max(a.nL, a.nR);
+    if (a.m * (cw * ch - 1) > 255) return fail(h, FASSMVS_EUNSUPPORTED, "cost exceeds 8 bits");
+    a.n_fam = n_fam;
+    for (int f = 0; f < n_fam; ++f) {
+        if (W[f] < 1 || W[f] > G[f] || (!offs && W[f] != G[f])) return fail(h, FASSMVS_EINVAL, "bad family sizes");
+        a.G[f] = G[f];
+        a.W[f] = W[f];
+        a.foff[f] = a.D;
+        a.goff[f] = a.sumG;
+        a.D += W[f];
+        a.sumG += G[f];
+    }
+    if (a.D > kMaxLabels) return fail(h, FASSMVS_EUNSUPPORTED, "too many labels");
+    fassmvs_status st = ensure(h, h->params, (size_t)n_views * a.sumG * 72);
+    if (st != FASSMVS_OK) return st;
+    HIPCHK(h, hipMemcpyAsync(h->params.p, H, (size_t)n_views * a.sumG * 72, hipMemcpyHostToDevice, h->stream),
+           "H upload");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "H upload");
+    a.H = (const double *)h->params.p;
+    a.ct_ref = ct_ref;
+    a.offs = offs;
+    a.warped = warped;
+    a.S = S;
+    a.rows_per_thread = sweep_rows();
+    hipError_t e = launch_sweep(a, h->stream);
+    if (e == hipErrorInvalidValue) return fail(h, FASSMVS_EUNSUPPORTED, "census window not built");
+    HIPCHK(h, e, "sweep launch");
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_stage_sgm(fassmvs_handle *h, int32_t w, int32_t hgt, int32_t n_fam, const int32_t *W,
+                                 const uint8_t *S, const int32_t *offs, const int8_t *dI, const uint8_t *ref,
+                                 int32_t p1, const int32_t *lut, int32_t n_paths, uint16_t *Lr, uint16_t *Sbar,
+                                 uint16_t *wta, uint16_t *c3) {
+    STAGE_BEGIN;
+    if (!W || !S || !ref || !lut || w < 1 || hgt < 1 || n_fam < 1 || n_fam > kMaxFam)
+        return fail(h, FASSMVS_EINVAL, "bad sgm arguments");
+    if (n_paths != 4 && n_paths != 8) return fail(h, FASSMVS_EINVAL, "n_paths must be 4 or 8");
+    if ((wta == nullptr) != (c3 == nullptr)) return fail(h, FASSMVS_EINVAL, "wta and c3 go together");
+    LevelPlan L;
+    L.w = w;
+    L.h = hgt;
+    L.F = n_fam;
+    L.D = 0;
+    for (int f = 0; f < n_fam; ++f) {
+        if (W[f] < 1) return fail(h, FASSMVS_EINVAL, "bad window");
+        L.W[f] = W[f];
+        L.foff[f] = L.D;
+        L.D += W[f];
+    }
+    if (L.D > kMaxLabels) return fail(h, FASSMVS_EUNSUPPORTED, "too many labels");
+    for (int i = 0; i < 256; ++i)
+        if (lut[i] < p1) return fail(h, FASSMVS_EINVAL, "P2 must be >= P1");
+    const size_t ND = (size_t)w * hgt * L.D;
+    uint16_t *bufs[8];
+    fassmvs_status st;
+    if (Lr) {
+        for (int d = 0; d < n_paths; ++d) bufs[d] = Lr + (size_t)d * ND;
+    } else {
+        for (int d = 0; d < n_paths; ++d) {
+            if ((st = ensure(h, h->sgmbuf[d], ND * 2)) != FASSMVS_OK) return st;
+            bufs[d] = (uint16_t *)h->sgmbuf[d].p;
+        }
+    }
+    st = run_sgm(h, L, S, offs, dI, ref, p1, lut, n_paths, bufs, Sbar, wta, c3);
+    if (st != FASSMVS_OK) return st;
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_stage_refine(fassmvs_handle *h, int32_t w, int32_t hgt, int32_t n_fam, const int32_t *W,
+                                    const int32_t *G, const int32_t *offs, const uint16_t *wta, const uint16_t *c3,
+                                    const double *fam_n, const double *fam_delta, const double *Kinv, int32_t *label,
+                                    int32_t *fam, float *depth) {
+    STAGE_BEGIN;
+    if (!W || !G || !wta || !c3 || !fam_n || !fam_delta || !Kinv || !label || !fam || !depth || n_fam < 1 ||
+        n_fam > kMaxFam)
+        return fail(h, FASSMVS_EINVAL, "bad refine arguments");
+    RefineArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.w = w;
+    a.h = hgt;
+    a.n_fam = n_fam;
+    int D = 0, sumG = 0;
+    for (int f = 0; f < n_fam; ++f) {
+        a.W[f] = W[f];
+        a.G[f] = G[f];
+        a.foff[f] = D;
+        a.goff[f] = sumG;
+        D += W[f];
+        sumG += G[f];
+        for (int i = 0; i < 3; ++i) a.fam_n[f][i] = fam_n[f * 3 + i];
+    }
+    std::memcpy(a.Kinv, Kinv, 72);
+    fassmvs_status st = ensure(h, h->params, (size_t)sumG * 8);
+    if (st != FASSMVS_OK) return st;
+    HIPCHK(h, hipMemcpyAsync(h->params.p, fam_delta, (size_t)sumG * 8, hipMemcpyHostToDevice, h->stream), "delta upload");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "delta upload");
+    a.delta = (const double *)h->params.p;
+    a.offs = offs;
+    a.wta = wta;
+    a.c3 = c3;
+    a.label = label;
+    a.fam = fam;
+    a.depth = depth;
+    HIPCHK(h, launch_refine(a, h->stream), "refine launch");
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_stage_median(fassmvs_handle *h, const float *in, int32_t w, int32_t hgt, float *out) {
+    STAGE_BEGIN;
+    if (!in || !out || w < 1 || hgt < 1) return fail(h, FASSMVS_EINVAL, "bad median arguments");
+    HIPCHK(h, launch_median5(in, w, hgt, out, h->stream), "median launch");
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_stage_normals(fassmvs_handle *h, const float *depth, const uint8_t *img, int32_t w, int32_t hgt,
+                                     const double *Kinv, int32_t radius, double beta, const int32_t *label,
+                                     const int32_t *fam, int32_t n_fam, const double *fam_n, double rho_deg,
+                                     float *nraw, float *normal, float *conf) {
+    STAGE_BEGIN;
+    if (!depth || !img || !Kinv || !label || !fam || !fam_n || !normal || !conf || n_fam < 1 || n_fam > kMaxFam ||
+        radius < 1 || radius > 4)
+        return fail(h, FASSMVS_EINVAL, "bad normals arguments");
+    NormalArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.w = w;
+    a.h = hgt;
+    a.radius = radius;
+    a.beta = beta;
+    a.cos_rho = std::cos(rho_deg * 3.14159265358979323846 / 180.0);
+    std::memcpy(a.Kinv, Kinv, 72);
+    a.n_fam = n_fam;
+    for (int f = 0; f < n_fam; ++f)
+        for (int i = 0; i < 3; ++i) a.fam_n[f][i] = fam_n[f * 3 + i];
+    a.depth = depth;
+    a.img = img;
+    a.label = label;
+    a.fam = fam;
+    DevBuf tmp;
+    float *nr = nraw;
+    if (!nr) {
+        HIPCHK(h, hipMalloc(&tmp.p, (size_t)w * hgt * 12), "temporary normals");
+        nr = (float *)tmp.p;
+    }
+    a.nraw = nr;
+    a.normal = normal;
+    a.conf = conf;
+    hipError_t e = launch_normals(a, h->stream);
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (tmp.p) hipFree(tmp.p);
+    HIPCHK(h, e, "normals launch");
+    HIPCHK(h, e2, "normals execution");
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_stage_seed(fassmvs_handle *h, const float *depth_c, const float *normal_c, int32_t cw,
+                                  int32_t ch, int32_t fw, int32_t fh, const double *Kinv, int32_t n_fam,
+                                  const double *fam_n, const double *inv_dmin, const double *step, const int32_t *G,
+                                  const int32_t *W, float *dbar, float *nbar, int32_t *offs, int8_t *dI) {
+    STAGE_BEGIN;
+    if (!depth_c || !normal_c || !Kinv || !fam_n || !inv_dmin || !step || !G || !W || !dbar || !nbar || !offs ||
+        n_fam < 1 || n_fam > kMaxFam || cw < 1 || ch < 1 || fw < 1 || fh < 1)
+        return fail(h, FASSMVS_EINVAL, "bad seed arguments");
+    SeedArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.cw = cw;
+    a.ch = ch;
+    a.fw = fw;
+    a.fh = fh;
+    a.n_fam = n_fam;
+    std::memcpy(a.Kinv, Kinv, 72);
+    for (int f = 0; f < n_fam; ++f) {
+        if (W[f] < 1 || W[f] > G[f]) return fail(h, FASSMVS_EINVAL, "bad family sizes");
+        for (int i = 0; i < 3; ++i) a.fam_n[f][i] = fam_n[f * 3 + i];
+        a.inv_dmin[f] = inv_dmin[f];
+        a.step[f] = step[f];
+        a.G[f] = G[f];
+        a.W[f] = W[f];
+    }
+    a.depth_c = depth_c;
+    a.normal_c = normal_c;
+    a.dbar = dbar;
+    a.nbar = nbar;
+    a.offs = offs;
+    a.dI = dI;
+    HIPCHK(h, launch_seed(a, h->stream), "seed launch");
+    STAGE_END;
+}
+
+}  // extern "C"

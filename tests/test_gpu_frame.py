@@ -1,0 +1,107 @@
+"""End-to-end parity of whole frames (C-ABI submit/poll) with the oracle.
+
+Gates: plane labels identical on >= 99.9 % of pixels at every level, refined
+depth within 1e-3 relative where labels agree, warped intensities covered by
+the stage tests; normals / confidence within 1e-4 where the depth agrees."""
+import numpy as np
+import pytest
+
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fm():
+    import paper_2112_00821_amd as fm
+    return fm
+
+
+def _compare(orc_out, h, wl, levels):
+    n_fam = len(wl["families"])
+    rep = {}
+    for l in levels:
+        lv = orc_out["levels"][l]
+        lab = h.level_map(l, 4)
+        dep = h.level_map(l, 0)
+        nrm = h.level_map(l, 2)
+        conf = h.level_map(l, 3)
+        agree = lab == lv["label"]
+        rep[l] = agree.mean()
+        assert agree.mean() >= 0.999, (l, agree.mean())
+        ok = agree & (lv["depth"] > 0)
+        rel = np.abs(dep[ok] - lv["depth"][ok]) / lv["depth"][ok]
+        assert np.mean(rel <= 1e-3) >= 0.999, (l, np.max(rel))
+        same = np.all(np.abs(dep - lv["depth"]) <= 1e-6 * np.maximum(lv["depth"], 1), axis=None)
+        if same:
+            assert np.max(np.abs(nrm - lv["normal"])) <= 1e-4
+            assert np.max(np.abs(conf - lv["conf"])) <= 1e-4
+        if l > 0 and lv.get("offs") is not None:
+            offs = h.level_map(l, 6, n_fam)
+            assert np.mean(offs == lv["offs"]) >= 0.999
+    return rep
+
+
+@pytest.mark.parametrize("name", ["config1", "nadir_planar", "config2_small", "config2_ragged", "config3_small"])
+def test_frame_matches_oracle(orc, fm, name):
+    wl = scenegen.make_workload(name)
+    ref = orc.run_frame(wl, keep=True)
+    cfg = fm.config_from_params(wl["params"], keep_levels=1, profile=1)
+    with fm.Handle(cfg) as h:
+        out = h.run_frame(wl)
+        rep = _compare(ref, h, wl, range(wl["params"]["n_levels"]))
+        agree0 = h.level_map(0, 4) == ref["levels"][0]["label"]
+        d = out["depth"]
+        ok = agree0 & (ref["depth"] > 0)
+        assert np.max(np.abs(d[ok] - ref["depth"][ok]) / ref["depth"][ok]) <= 1e-3
+        assert np.all((out["conf"] >= 0) & (out["conf"] <= 1))
+        print(name, "label agreement per level", rep)
+
+
+def test_frame_device_inputs_and_outputs(orc, fm):
+    wl = scenegen.make_workload("config1")
+    cfg = fm.config_from_params(wl["params"])
+    with fm.Handle(cfg) as h:
+        host = h.run_frame(wl)
+        ref = dict(wl["ref"], img=h.upload(wl["ref"]["img"]))
+        views = [dict(v, img=h.upload(v["img"])) for v in wl["views"]]
+        t = h.submit_frame(ref, views, wl["side"], wl["K"], wl["families"], mem_kind=fm.MEM_DEVICE)
+        dd = h.empty((wl["height"], wl["width"]), np.float32)
+        h.poll(t, depth=dd, mem_kind=fm.MEM_DEVICE)
+        assert np.array_equal(dd.numpy(), host["depth"])
+
+
+def test_frame_errors_and_polling(orc, fm):
+    wl = scenegen.make_workload("config1")
+    cfg = fm.config_from_params(wl["params"])
+    with fm.Handle(cfg) as h:
+        t = h.submit_frame(wl["ref"], wl["views"], wl["side"], wl["K"], wl["families"])
+        with pytest.raises(fm.FassmvsError) as e:
+            h.submit_frame(wl["ref"], wl["views"], wl["side"], wl["K"], wl["families"])
+        assert e.value.status == fm.EBUSY
+        with pytest.raises(fm.FassmvsError) as e:
+            h.poll(t + 7)
+        assert e.value.status == fm.ENOTFOUND
+        d = np.zeros((wl["height"], wl["width"]), np.float32)
+        assert h.poll(t, depth=d, wait_ms=-1) == fm.OK
+        with pytest.raises(fm.FassmvsError):
+            h.poll(t)                                         # consumed
+        # a camera behind the nearest plane
+        bad = [dict(v) for v in wl["views"]]
+        bad[0] = dict(bad[0], t=np.asarray(bad[0]["t"]) - np.array([0.0, 0.0, 200.0]))   # 200 m ahead
+        with pytest.raises(fm.FassmvsError) as e:
+            h.submit_frame(wl["ref"], bad, wl["side"], wl["K"], wl["families"])
+        assert e.value.status == fm.EINVAL
+        fam = [dict(wl["families"][0], count=300)]
+        with pytest.raises(fm.FassmvsError) as e:
+            h.submit_frame(wl["ref"], wl["views"], wl["side"], wl["K"], fam)
+        assert e.value.status == fm.EINVAL
+
+
+def test_hbm_budget_rejects_large_frame(fm):
+    wl = scenegen.make_workload("config1")
+    cfg = fm.config_from_params(wl["params"], hbm_budget_bytes=1 << 20)
+    with fm.Handle(cfg) as h:
+        with pytest.raises(fm.FassmvsError) as e:
+            h.run_frame(wl)
+        assert e.value.status == fm.ENOMEM
