@@ -48,6 +48,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before timing, copy this many MiB device-to-device once (a plain copy kernel of known "
+                         "size whose HBM byte counters calibrate the profiler's FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the hot path does not shard across GPUs); got --gpus {args.gpus}",
@@ -66,6 +69,13 @@ def main():
         depth = hd.empty((h, w), np.float32)
         normal = hd.empty((h, w, 3), np.float32)
         conf = hd.empty((h, w), np.float32)
+
+        if args.calib_copy_mb:
+            nb = args.calib_copy_mb << 20
+            a_ = hd.empty((nb,), np.uint8).fill(1)
+            b_ = hd.empty((nb,), np.uint8)
+            fm.lib().fassmvs_memcpy(hd.h, b_.vp, a_.vp, nb, 2)
+            del a_, b_
 
         def step():
             t = hd.submit_frame(ref, views, wl["side"], wl["K"], wl["families"], mem_kind=fm.MEM_DEVICE)

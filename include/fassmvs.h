@@ -63,7 +63,7 @@ typedef struct {
     int32_t census_w;          /* census window width, 5 or 9 (similarity-measure experiment) */
     int32_t census_h;          /* census window height, 5 or 7 */
     int32_t n_paths;           /* 8, or 4 (diagonals dropped) */
-    int32_t sgm_variant;       /* 0: SGM^Pi; 1: SGM^Pi-sn below the coarsest level */
+    int32_t sgm_variant;       /* 0: SGM^Pi; 1: SGM^Pi-sn below the coarsest level; 2: SGM^Pi-pg */
     int32_t p1;                /* P1 per matching image; scaled by m = max(|L|,|R|) */
     int32_t p2_mode;           /* 0: fixed P2; 1: adaptive P2 (Eq. p2-grad) */
     int32_t p2_fixed;          /* P2 per matching image in fixed mode (>= p1) */
@@ -242,6 +242,18 @@ fassmvs_status fassmvs_stage_sgm(fassmvs_handle *h, int32_t w, int32_t hgt, int3
                                  const uint8_t *S, const int32_t *offs, const int8_t *dI, const uint8_t *ref,
                                  int32_t p1, const int32_t *lut, int32_t n_paths, uint16_t *Lr, uint16_t *Sbar,
                                  uint16_t *wta, uint16_t *c3);
+
+/* SGM^Pi-pg (Eq. sgm-smooth-pg): as fassmvs_stage_sgm, with the zero-cost
+ * transition shifted by the path-gradient offset -- the inverse depth of the
+ * path's two previous minimum-cost points, extrapolated to the pixel and
+ * expressed as a plane-index jump per family (rounded, clamped to +-7).
+ * Host arrays: G [F] list sizes, fam_delta (concatenated lists, sum G <= 2048),
+ * fam_n [F][3], Kinv [9] of the level, step [F] (inverse-distance step). */
+fassmvs_status fassmvs_stage_sgm_pg(fassmvs_handle *h, int32_t w, int32_t hgt, int32_t n_fam, const int32_t *W,
+                                    const int32_t *G, const uint8_t *S, const int32_t *offs, const uint8_t *ref,
+                                    int32_t p1, const int32_t *lut, int32_t n_paths, const double *fam_delta,
+                                    const double *fam_n, const double *Kinv, const double *step, uint16_t *Lr,
+                                    uint16_t *Sbar, uint16_t *wta, uint16_t *c3);
 
 /* Depth of the winning plane and parabola refinement (depth extraction for
  * SGM^Pi; depth refinement): from wta and c3 of fassmvs_stage_sgm.  Host

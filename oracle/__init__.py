@@ -70,6 +70,7 @@ def _declare(L):
         "or_cost_sample": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, i, i, i, i]),
         "or_cost_pixels": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, vp, vp, i, vp, vp]),
         "or_sgm": (i, [i, i, i, vp, vp, vp, vp, i, vp, vp, i, vp, vp]),
+        "or_sgm_pg": (i, [i, i, i, vp, vp, vp, vp, i, vp, vp, i, vp, vp, i, vp, vp, vp, vp, vp]),
         "or_wta_refine": (None, [i, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "or_median5": (None, [vp, i, i, vp]),
         "or_normals": (None, [vp, i, i, vp, vp]),
@@ -209,14 +210,24 @@ def cost_pixels(ct_ref, views, side, cw, ch, G, W, H, xy, offs=None):
     return out
 
 
-def sgm(S, W, p1, lut, ref, n_paths, offs=None, dI=None, want_sbar=True, want_lr=False):
+def sgm(S, W, p1, lut, ref, n_paths, offs=None, dI=None, want_sbar=True, want_lr=False, pg=None):
+    """Semi-global aggregation.  pg: None, or a dict with the level geometry
+    (G, fam_delta, fam_n, Kinv, step) to add the path-gradient offsets."""
     h, w, D = S.shape
     W = np.asarray(W, np.int32)
     Sbar = np.zeros((h, w, D), np.uint16) if want_sbar else None
     Lr = np.zeros((n_paths, h, w, D), np.uint16) if want_lr else None
-    r = lib().or_sgm(w, h, len(W), _p(W), _p(_c(offs, np.int32) if offs is not None else None),
-                     _p(_c(S, np.uint8)), _p(_c(dI, np.int8) if dI is not None else None), int(p1),
-                     _p(_c(lut, np.int32)), _p(_c(ref, np.uint8)), int(n_paths), _p(Sbar), _p(Lr))
+    args = [w, h, len(W), _p(W), _p(_c(offs, np.int32) if offs is not None else None),
+            _p(_c(S, np.uint8)), _p(_c(dI, np.int8) if dI is not None else None), int(p1),
+            _p(_c(lut, np.int32)), _p(_c(ref, np.uint8)), int(n_paths), _p(Sbar), _p(Lr)]
+    if pg is None:
+        r = lib().or_sgm(*args)
+    else:
+        G = np.asarray(pg["G"], np.int32)
+        goff = np.concatenate([[0], np.cumsum(G)[:-1]]).astype(np.int32)
+        keep = [goff, _c(pg["fam_delta"], np.float64), _c(pg["fam_n"], np.float64), _c(pg["Kinv"], np.float64),
+                _c(pg["step"], np.float64)]
+        r = lib().or_sgm_pg(*args, 1, *[_p(a) for a in keep])
     if r != 0:
         raise OverflowError("aggregated cost exceeds 16 bits")
     return Sbar, Lr
@@ -367,8 +378,11 @@ def run_frame(wl, keep=False, levels_only=None):
         o = None if top or p["window_labels"] <= 0 else offs
         S = cost_volume(ct, [pv[l] for pv in pyr_views], side, cw, chh, plan["G"], plan["W"], H, o)
         use_dI = (not top) and p["sgm_variant"] == 1 and dI is not None
-        Sbar, _ = sgm(S, plan["W"], p1, lut, img, p["n_paths"], offs=o, dI=dI if use_dI else None)
         fam_delta = np.concatenate(plan["deltas"])
+        pg = None
+        if p["sgm_variant"] == 2:
+            pg = dict(G=plan["G"], fam_delta=fam_delta, fam_n=plan["fam_n"], Kinv=Ki, step=plan["step"])
+        Sbar, _ = sgm(S, plan["W"], p1, lut, img, p["n_paths"], offs=o, dI=dI if use_dI else None, pg=pg)
         label, fam, depth_raw = wta_refine(Sbar, plan["W"], plan["G"], plan["fam_n"], fam_delta, Ki, o)
         depth = median5(depth_raw) if p["median"] else depth_raw
         nraw = normals(depth, Ki)
@@ -379,8 +393,6 @@ def run_frame(wl, keep=False, levels_only=None):
             rec.update(S=S, Sbar=Sbar, depth_raw=depth_raw, normal_raw=nraw, ct=ct, offs=o,
                        dI=dI if use_dI else None, H=H, plan=plan, img=img)
         out["levels"][l] = rec
-        if levels_only is not None and l == levels_only:
-            break
         if l > 0:
             fh, fw = pyr_ref[l - 1].shape
             dbar = upsample_nn(depth, fw, fh)
@@ -392,6 +404,8 @@ def run_frame(wl, keep=False, levels_only=None):
             dI = delta_i(dbar, nbar, Ki_f, plan_f["fam_n"], plan_f["step"]) if p["sgm_variant"] == 1 else None
             if keep:
                 out["levels"][l]["seed"] = dict(dbar=dbar, nbar=nbar, offs=offs, dI=dI)
+        if levels_only is not None and l == levels_only:
+            break
     if 0 in out["levels"]:
         lv = out["levels"][0]
         out["depth"], out["normal"], out["conf"] = lv["depth"], lv["normal"], lv["conf"]

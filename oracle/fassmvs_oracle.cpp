@@ -40,29 +40,25 @@ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v
 // Warped sample (Alg. 1, patch warping by the plane-induced homography).
 // The reference-grid point (qx, qy) (pixel-centre coordinates) maps through H
 // to (hx/hz, hy/hz) in the view's pixel-centre coordinates; the view is
-// sampled bilinearly with clamp-to-edge addressing.  Points that map behind
-// the view camera (hz <= 0) are treated as lying outside the image at the
-// top-left corner.  Intensities stay on the 0..255 scale.
+// sampled bilinearly with clamp-to-edge addressing.  The paper fixes no
+// rounding; this definition fixes every operation (fused multiply-adds for
+// the homography rows, the coordinate shift and the interpolation, one
+// correctly rounded reciprocal) so that a census bit taken from the sample
+// is reproducible.  Points that map behind (or onto the focal plane of) the
+// view camera, hz <= 1e-300, get reciprocal 0, which lands them on the
+// top-left corner; the threshold keeps the reciprocal finite.  Clamping the
+// coordinate to [-1, size] leaves the clamp-to-edge bilinear value unchanged
+// and keeps every index finite.  Intensities stay on the 0..255 scale.
 // ---------------------------------------------------------------------------
 float warp_sample(const uint8_t* src, int sw, int sh, const double* H, double qx, double qy) {
-    double hx = H[0] * qx + H[1] * qy + H[2];
-    double hy = H[3] * qx + H[4] * qy + H[5];
-    double hz = H[6] * qx + H[7] * qy + H[8];
-    double sx, sy;
-    if (hz > 0.0) {
-        double inv = 1.0 / hz;
-        sx = hx * inv - 0.5;
-        sy = hy * inv - 0.5;
-    } else {
-        sx = -1.0;
-        sy = -1.0;
-    }
-    // clamping the coordinate to [-1, size] leaves the clamp-to-edge
-    // bilinear value unchanged and keeps every index finite
+    double hx = std::fma(H[0], qx, std::fma(H[1], qy, H[2]));
+    double hy = std::fma(H[3], qx, std::fma(H[4], qy, H[5]));
+    double hz = std::fma(H[6], qx, std::fma(H[7], qy, H[8]));
+    double inv = hz > 1e-300 ? 1.0 / hz : 0.0;
+    double sx = std::fma(hx, inv, -0.5);
+    double sy = std::fma(hy, inv, -0.5);
     sx = std::min(std::max(sx, -1.0), (double)sw);
     sy = std::min(std::max(sy, -1.0), (double)sh);
-    if (std::isnan(sx)) sx = -1.0;
-    if (std::isnan(sy)) sy = -1.0;
     double fx0 = std::floor(sx);
     double fy0 = std::floor(sy);
     int x0 = (int)fx0, y0 = (int)fy0;
@@ -74,9 +70,9 @@ float warp_sample(const uint8_t* src, int sw, int sh, const double* H, double qx
     float i10 = (float)src[(size_t)ya * sw + xb];
     float i01 = (float)src[(size_t)yb * sw + xa];
     float i11 = (float)src[(size_t)yb * sw + xb];
-    float top = i00 + ax * (i10 - i00);
-    float bot = i01 + ax * (i11 - i01);
-    return top + ay * (bot - top);
+    float top = std::fma(ax, i10 - i00, i00);
+    float bot = std::fma(ax, i11 - i01, i01);
+    return std::fma(ay, bot - top, top);
 }
 
 // census word of a float image at (x, y), window cw x ch (odd), replicate border
@@ -398,9 +394,34 @@ int or_cost_pixels(int w, int h, const uint64_t* ct_ref, int n_views, const uint
 //   dI: [8][h][w][n_fam] int8 or NULL (all zero).  P2 = lut[|I(p) - I(q)|].
 // Returns 0, or -2 if an aggregate exceeds 16 bits.
 // ---------------------------------------------------------------------------
+int or_sgm_pg(int w, int h, int n_fam, const int* W, const int32_t* offs, const uint8_t* S,
+              const int8_t* dI, int p1, const int32_t* lut, const uint8_t* ref, int n_paths,
+              uint16_t* Sbar, uint16_t* Lr_out, int pg, const int* goff, const double* fam_delta,
+              const double* fam_n, const double* Kinv, const double* step);
+
 int or_sgm(int w, int h, int n_fam, const int* W, const int32_t* offs, const uint8_t* S,
            const int8_t* dI, int p1, const int32_t* lut, const uint8_t* ref, int n_paths,
            uint16_t* Sbar, uint16_t* Lr_out) {
+    return or_sgm_pg(w, h, n_fam, W, offs, S, dI, p1, lut, ref, n_paths, Sbar, Lr_out, 0, nullptr, nullptr,
+                     nullptr, nullptr, nullptr);
+}
+
+// Path-gradient variant (Eq. sgm-smooth-pg), reading of the unspecified
+// index jump: along a path, the minimum-cost planes of the two previous
+// pixels q = p - r and q2 = q - r give depths d_q and d_q2; continuing the
+// path's scene-space gradient (for a planar surface inverse depth is affine
+// in the pixel, so the extrapolated inverse depth 1/d* = 2/d_q - 1/d_q2 is
+// exact) gives the expected point on p's ray; di_pg(p, r, f) =
+// round-half-away((1/delta_p - 1/delta_q)/step_f) with 1/delta_q of q's point
+// and 1/delta_p = (1/d*) / c_p of the expected point in family f (the plane
+// index is affine in inverse distance, so this holds beyond infinite depth
+// too), clamped to [-7, 7] -- the same form as the surface-normal offset.
+// Zero on the first two pixels of a path and where a depth is missing.
+// pg = 1 adds it to the shift; the geometry arguments may then not be NULL.
+int or_sgm_pg(int w, int h, int n_fam, const int* W, const int32_t* offs, const uint8_t* S,
+              const int8_t* dI, int p1, const int32_t* lut, const uint8_t* ref, int n_paths,
+              uint16_t* Sbar, uint16_t* Lr_out, int pg, const int* goff, const double* fam_delta,
+              const double* fam_n, const double* Kinv, const double* step) {
     static const int DX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
     static const int DY[8] = {0, 0, 1, -1, 1, -1, -1, 1};
     int D = 0;
@@ -408,6 +429,7 @@ int or_sgm(int w, int h, int n_fam, const int* W, const int32_t* offs, const uin
     for (int f = 0; f < n_fam; ++f) { foff[f] = D; D += W[f]; }
     size_t N = (size_t)w * h;
     std::vector<int64_t> acc(N * D, 0), L(N * D, 0);
+    std::vector<double> dhat(pg ? N : 0, 0.0);   // depth of each pixel's minimum-cost plane on this path
     for (int r = 0; r < n_paths; ++r) {
         int dx = DX[r], dy = DY[r];
         for (int yi = 0; yi < h; ++yi) {
@@ -418,28 +440,71 @@ int or_sgm(int w, int h, int n_fam, const int* W, const int32_t* offs, const uin
                 int qx = x - dx, qy = y - dy;
                 if (qx < 0 || qx >= w || qy < 0 || qy >= h) {
                     for (int i = 0; i < D; ++i) L[p * D + i] = S[p * D + i];
-                    continue;
-                }
-                size_t q = (size_t)qy * w + qx;
-                int64_t Mq = L[q * D];
-                for (int i = 1; i < D; ++i) Mq = std::min(Mq, L[q * D + i]);
-                int dint = std::abs((int)ref[p] - (int)ref[q]);
-                int64_t P2 = lut[dint];
-                for (int f = 0; f < n_fam; ++f) {
-                    int op = offs ? offs[(size_t)f * N + p] : 0;
-                    int oq = offs ? offs[(size_t)f * N + q] : 0;
-                    int di = dI ? dI[(((size_t)r * N) + p) * n_fam + f] : 0;
-                    for (int i = 0; i < W[f]; ++i) {
-                        int target = op + i + di;       // global index of the zero-cost predecessor
-                        int64_t best = Mq + P2;
-                        for (int e = -1; e <= 1; ++e) {
-                            int j = target + e - oq;    // local index in q's window
-                            if (j < 0 || j >= W[f]) continue;
-                            int64_t c = L[q * D + foff[f] + j] + (e == 0 ? 0 : p1);
-                            best = std::min(best, c);
+                } else {
+                    size_t q = (size_t)qy * w + qx;
+                    int64_t Mq = L[q * D];
+                    for (int i = 1; i < D; ++i) Mq = std::min(Mq, L[q * D + i]);
+                    int dint = std::abs((int)ref[p] - (int)ref[q]);
+                    int64_t P2 = lut[dint];
+                    // path-gradient offsets from the two previous minimum-cost points
+                    int pgdi[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    int q2x = qx - dx, q2y = qy - dy;
+                    if (pg && q2x >= 0 && q2x < w && q2y >= 0 && q2y < h) {
+                        double d1 = dhat[q], d2 = dhat[(size_t)q2y * w + q2x];
+                        if (d1 > 0.0 && d2 > 0.0) {
+                            double inv = 2.0 / d1 - 1.0 / d2;   // extrapolated inverse depth
+                            double rp[3], rq[3];
+                            rp[0] = Kinv[0] * (x + 0.5) + Kinv[1] * (y + 0.5) + Kinv[2];
+                            rp[1] = Kinv[3] * (x + 0.5) + Kinv[4] * (y + 0.5) + Kinv[5];
+                            rp[2] = Kinv[6] * (x + 0.5) + Kinv[7] * (y + 0.5) + Kinv[8];
+                            rq[0] = Kinv[0] * (qx + 0.5) + Kinv[1] * (qy + 0.5) + Kinv[2];
+                            rq[1] = Kinv[3] * (qx + 0.5) + Kinv[4] * (qy + 0.5) + Kinv[5];
+                            rq[2] = Kinv[6] * (qx + 0.5) + Kinv[7] * (qy + 0.5) + Kinv[8];
+                            for (int f = 0; f < n_fam; ++f) {
+                                const double* n = fam_n + 3 * f;
+                                double cp = -(n[0] * rp[0] + n[1] * rp[1] + n[2] * rp[2]);
+                                double cq = -(n[0] * rq[0] + n[1] * rq[1] + n[2] * rq[2]);
+                                if (!(cp > 0.0) || !(cq > 0.0)) continue;
+                                double ip = inv / cp;
+                                double iq = 1.0 / (d1 * cq);
+                                double v = (ip - iq) / step[f];
+                                v = std::min(std::max(v, -7.0), 7.0);
+                                pgdi[f] = (int)std::round(v);
+                            }
                         }
-                        L[p * D + foff[f] + i] = (int64_t)S[p * D + foff[f] + i] + best - Mq;
                     }
+                    for (int f = 0; f < n_fam; ++f) {
+                        int op = offs ? offs[(size_t)f * N + p] : 0;
+                        int oq = offs ? offs[(size_t)f * N + q] : 0;
+                        int di = (dI ? dI[(((size_t)r * N) + p) * n_fam + f] : 0) + pgdi[f];
+                        for (int i = 0; i < W[f]; ++i) {
+                            int target = op + i + di;       // global index of the zero-cost predecessor
+                            int64_t best = Mq + P2;
+                            for (int e = -1; e <= 1; ++e) {
+                                int j = target + e - oq;    // local index in q's window
+                                if (j < 0 || j >= W[f]) continue;
+                                int64_t c = L[q * D + foff[f] + j] + (e == 0 ? 0 : p1);
+                                best = std::min(best, c);
+                            }
+                            L[p * D + foff[f] + i] = (int64_t)S[p * D + foff[f] + i] + best - Mq;
+                        }
+                    }
+                }
+                if (pg) {
+                    // depth of this pixel's minimum-cost plane (smallest label on ties)
+                    int bi = 0;
+                    for (int i = 1; i < D; ++i)
+                        if (L[p * D + i] < L[p * D + bi]) bi = i;
+                    int f = 0;
+                    while (f + 1 < n_fam && bi >= foff[f + 1]) ++f;
+                    int g = (offs ? offs[(size_t)f * N + p] : 0) + (bi - foff[f]);
+                    const double* n = fam_n + 3 * f;
+                    double rr[3];
+                    rr[0] = Kinv[0] * (x + 0.5) + Kinv[1] * (y + 0.5) + Kinv[2];
+                    rr[1] = Kinv[3] * (x + 0.5) + Kinv[4] * (y + 0.5) + Kinv[5];
+                    rr[2] = Kinv[6] * (x + 0.5) + Kinv[7] * (y + 0.5) + Kinv[8];
+                    double den = n[0] * rr[0] + n[1] * rr[1] + n[2] * rr[2];
+                    dhat[p] = (den < 0.0) ? -fam_delta[goff[f] + g] / den : 0.0;
                 }
             }
         }

@@ -90,6 +90,8 @@ def _declare(L):
         "fassmvs_stage_warp": (st, [vp, vp, i32, i32, vp, i32, i32, vp]),
         "fassmvs_stage_cost": (st, [vp, i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "fassmvs_stage_sgm": (st, [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]),
+        "fassmvs_stage_sgm_pg": (st, [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp,
+                                      vp, vp]),
         "fassmvs_stage_refine": (st, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "fassmvs_stage_median": (st, [vp, vp, i32, i32, vp]),
         "fassmvs_stage_normals": (st, [vp, vp, vp, i32, i32, vp, i32, dbl, vp, vp, i32, vp, dbl, vp, vp, vp]),
@@ -371,6 +373,24 @@ class Handle:
         c3 = self.empty((h, w, 3), np.uint16) if want_wta else None
         self._check(lib().fassmvs_stage_sgm(self.h, w, h, len(Wa), Wp, S.vp, _vp(offs), _vp(dI), ref.vp, int(p1), lp,
                                             n_paths, _vp(Lr), _vp(Sbar), _vp(wta), _vp(c3)))
+        return dict(Lr=Lr, Sbar=Sbar, wta=wta, c3=c3)
+
+    def stage_sgm_pg(self, S: DeviceArray, W, G, p1, lut, ref: DeviceArray, n_paths, fam_delta, fam_n, Kinv, step,
+                     offs=None, want_lr=False, want_sbar=False, want_wta=True):
+        h, w, D = S.shape
+        Wa, Wp = _arr(W, np.int32)
+        Ga, Gp = _arr(G, np.int32)
+        la, lp = _arr(lut, np.int32)
+        da, dp = _arr(fam_delta, np.float64)
+        na, npp = _arr(fam_n, np.float64)
+        ka, kp = _arr(Kinv, np.float64)
+        sa, sp = _arr(step, np.float64)
+        Lr = self.empty((n_paths, h, w, D), np.uint16) if want_lr else None
+        Sbar = self.empty((h, w, D), np.uint16) if want_sbar else None
+        wta = self.empty((h, w), np.uint16) if want_wta else None
+        c3 = self.empty((h, w, 3), np.uint16) if want_wta else None
+        self._check(lib().fassmvs_stage_sgm_pg(self.h, w, h, len(Wa), Wp, Gp, S.vp, _vp(offs), ref.vp, int(p1), lp,
+                                               n_paths, dp, npp, kp, sp, _vp(Lr), _vp(Sbar), _vp(wta), _vp(c3)))
         return dict(Lr=Lr, Sbar=Sbar, wta=wta, c3=c3)
 
     def stage_refine(self, wta, c3, W, G, fam_n, fam_delta, Kinv, offs=None):

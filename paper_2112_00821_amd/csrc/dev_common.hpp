@@ -10,43 +10,42 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 
 // Bilinear clamp-to-edge sample of an 8-bit view at the point the
 // homography H maps the reference-grid point (qx, qy) to (pixel-centre
-// coordinates on both sides).  The projective division runs in double; the
-// interpolation in float with a fixed operation order, so the census bits
-// that compare these values are reproducible.  Points mapped behind the
-// view (hz <= 0) read the top-left corner.  Result on the 0..255 scale.
+// coordinates on both sides).  Every operation is fixed: fused
+// multiply-adds for the homography rows, the coordinate shift and the
+// interpolation, and one correctly rounded double reciprocal, so the census
+// bits that compare these values are reproducible.  Points mapped behind the
+// view (hz <= 1e-300) get reciprocal 0 and read the top-left corner.
+// Branch-free; result on the 0..255 scale.
 __device__ __forceinline__ float warp_sample(const uint8_t *__restrict__ src, int sw, int sh, double h0, double h1,
                                              double h2, double h3, double h4, double h5, double h6, double h7,
                                              double h8, double qx, double qy) {
-    double hx = h0 * qx + h1 * qy + h2;
-    double hy = h3 * qx + h4 * qy + h5;
-    double hz = h6 * qx + h7 * qy + h8;
-    double sx, sy;
-    if (hz > 0.0) {
-        double inv = 1.0 / hz;
-        sx = hx * inv - 0.5;
-        sy = hy * inv - 0.5;
-    } else {
-        sx = -1.0;
-        sy = -1.0;
-    }
-    sx = fmin(fmax(sx, -1.0), (double)sw);
-    sy = fmin(fmax(sy, -1.0), (double)sh);
-    double fx0 = floor(sx);
-    double fy0 = floor(sy);
-    int x0 = (int)fx0, y0 = (int)fy0;
-    float ax = (float)(sx - fx0);
-    float ay = (float)(sy - fy0);
-    int xa = clampi(x0, 0, sw - 1), xb = clampi(x0 + 1, 0, sw - 1);
-    int ya = clampi(y0, 0, sh - 1), yb = clampi(y0 + 1, 0, sh - 1);
-    const uint8_t *ra = src + (size_t)ya * sw;
-    const uint8_t *rb = src + (size_t)yb * sw;
-    float i00 = (float)ra[xa];
-    float i10 = (float)ra[xb];
-    float i01 = (float)rb[xa];
-    float i11 = (float)rb[xb];
-    float top = i00 + ax * (i10 - i00);
-    float bot = i01 + ax * (i11 - i01);
-    return top + ay * (bot - top);
+    const double hx = __builtin_fma(h0, qx, __builtin_fma(h1, qy, h2));
+    const double hy = __builtin_fma(h3, qx, __builtin_fma(h4, qy, h5));
+    const double hz = __builtin_fma(h6, qx, __builtin_fma(h7, qy, h8));
+    const double r = 1.0 / hz;
+    const double inv = hz > 1e-300 ? r : 0.0;
+    // The coordinate is clamped to [0, size - 1] rather than [-1, size]:
+    // outside [0, size - 1] both bilinear neighbours of the clamp-to-edge
+    // sample are the same border pixel, so the value is that pixel whatever
+    // the fraction, and at the clamped coordinate the fraction is 0 and the
+    // left (top) neighbour is that pixel.  With a non-negative coordinate the
+    // truncating conversion is the floor.
+    double sx = __builtin_fma(hx, inv, -0.5);
+    double sy = __builtin_fma(hy, inv, -0.5);
+    sx = __builtin_fmin(__builtin_fmax(sx, 0.0), (double)(sw - 1));
+    sy = __builtin_fmin(__builtin_fmax(sy, 0.0), (double)(sh - 1));
+    const uint32_t xa = (uint32_t)(int)sx, ya = (uint32_t)(int)sy;
+    const float ax = (float)(sx - floor(sx));
+    const float ay = (float)(sy - floor(sy));
+    const uint32_t xb = min(xa + 1u, (uint32_t)(sw - 1)), yb = min(ya + 1u, (uint32_t)(sh - 1));
+    const uint32_t ra = __umul24(ya, (uint32_t)sw), rb = __umul24(yb, (uint32_t)sw);
+    const float i00 = (float)src[ra + xa];
+    const float i10 = (float)src[ra + xb];
+    const float i01 = (float)src[rb + xa];
+    const float i11 = (float)src[rb + xb];
+    const float top = __builtin_fmaf(ax, i10 - i00, i00);
+    const float bot = __builtin_fmaf(ax, i11 - i01, i01);
+    return __builtin_fmaf(ay, bot - top, top);
 }
 
 // Minimum over the 64 lanes of a wavefront: DPP within each row of 16, then

@@ -71,10 +71,17 @@ int sgm_paths(int dir, int w, int h) {
 // bytes, and the per-step uniform values (reference intensity, window
 // offsets, surface-normal offsets) of 64 steps are fetched by one vector
 // load per quantity (lane j holds step t0 + j) and read back with readlane.
-template <int K, bool WIN, bool SN>
+// NF bounds the plane families (1, or up to the maximum), which sizes the
+// per-family registers.
+template <int K, int NF, bool WIN, bool SN, bool PG>
 __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
     constexpr int PF = 8;
     __shared__ uint32_t lbuf[WAVES][2][LBUF];
+    __shared__ double pdelta[PG ? kMaxPgPlanes : 1];
+    if (PG) {
+        for (int i = threadIdx.x; i < a.sumG; i += 64 * WAVES) pdelta[i] = a.delta[i];
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int path = blockIdx.x * WAVES + wid;
@@ -85,7 +92,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
     const PathGeom pg = path_geom(dir, path - a.path_begin[slot], a.w, a.h);
     const size_t N = (size_t)a.w * a.h;
     const int D = a.D;
-    const int F = a.n_fam;
+    const int F = NF == 1 ? 1 : a.n_fam;
     const long pstride = (long)pg.dy * a.w + pg.dx;
     const long p0 = (long)pg.sy * a.w + pg.sx;
     const int len = pg.len;
@@ -117,18 +124,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
     uint16_t *__restrict__ out = a.out[slot];
 
     // per-step uniform values, 64 steps per chunk
-    auto load_chunk = [&](int t0, int &ref_v, int (&off_v)[kMaxFam], int (&di_v)[kMaxFam]) {
+    auto load_chunk = [&](int t0, int &ref_v, int (&off_v)[NF], int (&di_v)[NF]) {
         int t = t0 + lane;
         long p = p0 + (long)(t < len ? t : len - 1) * pstride;
         ref_v = a.ref[p];
 #pragma unroll
-        for (int f = 0; f < kMaxFam; ++f) {
+        for (int f = 0; f < NF; ++f) {
             off_v[f] = (WIN && f < F) ? a.offs[(size_t)f * N + p] : 0;
             di_v[f] = (SN && f < F) ? (int)a.dI[((size_t)dir * N + p) * F + f] : 0;
         }
     };
     int c_ref, n_ref;
-    int c_off[kMaxFam], n_off[kMaxFam], c_di[kMaxFam], n_di[kMaxFam];
+    int c_off[NF], n_off[NF], c_di[NF], n_di[NF];
     load_chunk(0, c_ref, c_off, c_di);
     if (len > 64) load_chunk(64, n_ref, n_off, n_di);
 
@@ -144,21 +151,23 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
     uint32_t L[K];
     uint32_t Mq = 0;
     int Iq = 0;
-    int oq[kMaxFam];
+    int oq[NF];
 #pragma unroll
-    for (int f = 0; f < kMaxFam; ++f) oq[f] = 0;
+    for (int f = 0; f < NF; ++f) oq[f] = 0;
+    // path-gradient state: depths of the last two minimum-cost points
+    double dq1 = 0.0, dq2 = 0.0;
 
     for (int t0 = 0; t0 < len; t0 += PF) {
         if (t0 > 0 && (t0 & 63) == 0) {
             c_ref = n_ref;
 #pragma unroll
-            for (int f = 0; f < kMaxFam; ++f) {
+            for (int f = 0; f < NF; ++f) {
                 c_off[f] = n_off[f];
                 c_di[f] = n_di[f];
             }
             if (t0 + 64 < len) load_chunk(t0 + 64, n_ref, n_off, n_di);
         }
-        const int lb = t0 & 63;
+        const int lb = t0 & 63;   // PF divides 64
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int t = t0 + u;
@@ -173,9 +182,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
                 for (int k = 0; k < K; ++k) ring[u][k] = lv[k] ? S[(size_t)pn * D + k * 64 + lane] : 0u;
             }
             const int Ip = __builtin_amdgcn_readlane(c_ref, lb + u);
-            int op[kMaxFam];
+            int op[NF];
 #pragma unroll
-            for (int f = 0; f < kMaxFam; ++f) op[f] = WIN ? __builtin_amdgcn_readlane(c_off[f], lb + u) : 0;
+            for (int f = 0; f < NF; ++f) op[f] = WIN ? __builtin_amdgcn_readlane(c_off[f], lb + u) : 0;
             uint32_t *cur = (t & 1) ? buf1 : buf0;
             const uint32_t *prev = (t & 1) ? buf0 : buf1;
             if (t == 0) {
@@ -185,19 +194,41 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
                 int dI = Ip - Iq;
                 const uint32_t P2 = (uint32_t)a.lut[dI < 0 ? -dI : dI];
                 const uint32_t P1 = (uint32_t)a.p1;
-                int sh[kMaxFam];
+                int sh[NF];
 #pragma unroll
-                for (int f = 0; f < kMaxFam; ++f) {
+                for (int f = 0; f < NF; ++f) {
                     int v = WIN ? op[f] - oq[f] : 0;
                     if (SN) v += __builtin_amdgcn_readlane(c_di[f], lb + u);
                     sh[f] = v;
+                }
+                if (PG && t >= 2 && dq1 > 0.0 && dq2 > 0.0) {
+                    // extrapolated inverse depth of the path's minimum-cost
+                    // points, as a plane-index jump per family
+                    const int px = pg.sx + t * pg.dx, py = pg.sy + t * pg.dy;
+                    double rp[3], rq[3];
+                    ray_of(a.Kinv, px + 0.5, py + 0.5, rp);
+                    ray_of(a.Kinv, (px - pg.dx) + 0.5, (py - pg.dy) + 0.5, rq);
+                    const double inv = 2.0 / dq1 - 1.0 / dq2;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        if (f >= F) break;
+                        const double *n = a.fam_n[f];
+                        const double cp = -(n[0] * rp[0] + n[1] * rp[1] + n[2] * rp[2]);
+                        const double cq = -(n[0] * rq[0] + n[1] * rq[1] + n[2] * rq[2]);
+                        if (!(cp > 0.0) || !(cq > 0.0)) continue;
+                        const double ip = inv / cp;
+                        const double iq = 1.0 / (dq1 * cq);
+                        double v = (ip - iq) / a.step[f];
+                        v = fmin(fmax(v, -7.0), 7.0);
+                        sh[f] += (int)round(v);
+                    }
                 }
                 const uint32_t floor2 = Mq + P2;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     int sft = sh[0];
 #pragma unroll
-                    for (int f = 1; f < kMaxFam; ++f)
+                    for (int f = 1; f < NF; ++f)
                         if (fam[k] == f) sft = sh[f];
                     int j = li[k] + sft;
                     j = j < -2 ? -2 : (j > wf[k] + 1 ? wf[k] + 1 : j);
@@ -222,10 +253,32 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
                 m = v < m ? v : m;
             }
             __builtin_amdgcn_wave_barrier();
-            Mq = wave_min_u32(m);
+            if (PG) {
+                // minimum and its label in one reduction (smallest label on ties)
+                uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t kk = lv[k] ? ((L[k] << 16) | (uint32_t)(k * 64 + lane)) : 0xFFFFFFFFu;
+                    key = kk < key ? kk : key;
+                }
+                key = wave_min_u32(key);
+                Mq = key >> 16;
+                const int bi = (int)(key & 0xFFFFu);
+                int f = 0;
+                while (f + 1 < F && bi >= a.foff[f + 1]) ++f;
+                const int g = (WIN ? op[f] : 0) + (bi - a.foff[f]);
+                const int px = pg.sx + t * pg.dx, py = pg.sy + t * pg.dy;
+                double rr[3];
+                ray_of(a.Kinv, px + 0.5, py + 0.5, rr);
+                const double den = a.fam_n[f][0] * rr[0] + a.fam_n[f][1] * rr[1] + a.fam_n[f][2] * rr[2];
+                dq2 = dq1;
+                dq1 = den < 0.0 ? -pdelta[a.goff[f] + g] / den : 0.0;
+            } else {
+                Mq = wave_min_u32(m);
+            }
             Iq = Ip;
 #pragma unroll
-            for (int f = 0; f < kMaxFam; ++f) oq[f] = op[f];
+            for (int f = 0; f < NF; ++f) oq[f] = op[f];
         }
     }
 }
@@ -279,22 +332,130 @@ __global__ __launch_bounds__(256) void k_wta(const SgmArgs a) {
     }
 }
 
+// Row-level (16-lane) minimum: every lane of a DPP row ends with its row's
+// minimum.
+__device__ __forceinline__ uint32_t row_min_u32(uint32_t v) {
+    uint32_t t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false);
+    v = v < t ? v : t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false);
+    v = v < t ? v : t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false);
+    v = v < t ? v : t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false);
+    return v < t ? v : t;
+}
+
+typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
+
+// Winner-takes-all for label counts that are a multiple of 8: a DPP row of
+// 16 lanes owns one pixel (4 pixels per wavefront, contiguous in memory);
+// each lane reads 8 labels of every direction buffer with one 16-byte load
+// and adds them as packed 16-bit pairs (the aggregate fits 16 bits by the
+// configuration's bound); argmin and the neighbours' aggregates come from
+// row-level DPP reductions.
+template <int NCH>
+__global__ __launch_bounds__(256) void k_wta16(const SgmArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int row = lane >> 4, l16 = lane & 15;
+    const size_t N = (size_t)a.w * a.h;
+    const int D = a.D;
+    const int nch = D >> 3;
+    const size_t waves = (size_t)gridDim.x * 4;
+    const size_t wid = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    for (size_t pb = wid * 4; pb < N; pb += waves * 4) {
+        const size_t p = pb + row;
+        const bool pv = p < N;
+        uint32_t key = 0xFFFFFFFFu;
+        uint32_t acc[NCH][4];
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+            const int c = l16 + 16 * j;
+            const bool cv = pv && c < nch;
+            ushort2_t s4[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                if (b < a.n_in && cv) {
+                    const uint4 v = *(const uint4 *)(a.in[b] + p * D + 8 * c);
+                    s4[0] += __builtin_bit_cast(ushort2_t, v.x);
+                    s4[1] += __builtin_bit_cast(ushort2_t, v.y);
+                    s4[2] += __builtin_bit_cast(ushort2_t, v.z);
+                    s4[3] += __builtin_bit_cast(ushort2_t, v.w);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                acc[j][e] = __builtin_bit_cast(uint32_t, s4[e]);
+                if (cv) {
+                    const uint32_t lo = acc[j][e] & 0xFFFFu, hi = acc[j][e] >> 16;
+                    const uint32_t i0 = (uint32_t)(8 * c + 2 * e);
+                    const uint32_t k0 = (lo << 16) | i0, k1 = (hi << 16) | (i0 + 1);
+                    key = k0 < key ? k0 : key;
+                    key = k1 < key ? k1 : key;
+                }
+            }
+        }
+        key = row_min_u32(key);
+        const int best = (int)(key & 0xFFFFu);
+        int f = 0;
+        while (f + 1 < a.n_fam && best >= a.foff[f + 1]) ++f;
+        const int l = best - a.foff[f];
+        const bool has_m = l >= 1, has_p = l + 1 < a.W[f];
+        uint32_t cm = 0xFFFFu, cp = 0xFFFFu;
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+            const int c = l16 + 16 * j;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int i = 8 * c + e;
+                const uint32_t v = (e & 1) ? (acc[j][e >> 1] >> 16) : (acc[j][e >> 1] & 0xFFFFu);
+                if (has_m && i == best - 1) cm = v;
+                if (has_p && i == best + 1) cp = v;
+            }
+        }
+        cm = row_min_u32(cm);
+        cp = row_min_u32(cp);
+        if (pv && l16 == 0) {
+            a.wta[p] = (uint16_t)best;
+            a.c3[3 * p] = (uint16_t)cm;
+            a.c3[3 * p + 1] = (uint16_t)(key >> 16);
+            a.c3[3 * p + 2] = (uint16_t)cp;
+        }
+    }
+}
+
 template <int K>
 static void launch_k(const SgmArgs &a, bool win, bool sn, dim3 grid, hipStream_t s) {
     if (a.final_mode) {
-        unsigned blocks = (unsigned)std::min<size_t>(((size_t)a.w * a.h + 3) / 4, 65536);
+        const size_t N = (size_t)a.w * a.h;
+        if ((a.D & 7) == 0) {
+            unsigned blocks = (unsigned)std::min<size_t>((N + 15) / 16, 65536);
+            const int ncb = ((a.D >> 3) + 15) / 16;   // 8-label chunks per lane
+            switch (ncb) {
+                case 1: hipLaunchKernelGGL((k_wta16<1>), dim3(blocks), dim3(256), 0, s, a); return;
+                case 2: hipLaunchKernelGGL((k_wta16<2>), dim3(blocks), dim3(256), 0, s, a); return;
+                case 3: hipLaunchKernelGGL((k_wta16<3>), dim3(blocks), dim3(256), 0, s, a); return;
+                default: hipLaunchKernelGGL((k_wta16<4>), dim3(blocks), dim3(256), 0, s, a); return;
+            }
+        }
+        unsigned blocks = (unsigned)std::min<size_t>((N + 3) / 4, 65536);
         hipLaunchKernelGGL((k_wta<K>), dim3(blocks), dim3(256), 0, s, a);
         return;
     }
-#define FMVS_SGM(W_, S_)                                                             \
-    if (win == W_ && sn == S_) {                                                     \
-        hipLaunchKernelGGL((k_sgm<K, W_, S_>), grid, dim3(64 * WAVES), 0, s, a);     \
-        return;                                                                      \
+#define FMVS_SGM(W_, S_, P_)                                                                  \
+    if (win == W_ && sn == S_ && (a.pg != 0) == P_) {                                         \
+        if (a.n_fam == 1)                                                                     \
+            hipLaunchKernelGGL((k_sgm<K, 1, W_, S_, P_>), grid, dim3(64 * WAVES), 0, s, a);   \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_sgm<K, kMaxFam, W_, S_, P_>), grid, dim3(64 * WAVES), 0, s, a); \
+        return;                                                                               \
     }
-    FMVS_SGM(false, false)
-    FMVS_SGM(true, false)
-    FMVS_SGM(false, true)
-    FMVS_SGM(true, true)
+    FMVS_SGM(false, false, false)
+    FMVS_SGM(true, false, false)
+    FMVS_SGM(false, true, false)
+    FMVS_SGM(true, true, false)
+    FMVS_SGM(false, false, true)
+    FMVS_SGM(true, false, true)
 #undef FMVS_SGM
 }
 
@@ -307,6 +468,7 @@ hipError_t launch_sgm(const SgmArgs &a0, hipStream_t s) {
     if (paths == 0 && !a.final_mode) return hipSuccess;
     dim3 grid((unsigned)((paths + WAVES - 1) / WAVES));
     bool win = a.offs != nullptr, sn = a.dI != nullptr;
+    if (a.pg && (sn || a.sumG > kMaxPgPlanes || !a.delta)) return hipErrorInvalidValue;
     int K = (a.D + 63) / 64;
     switch (K) {
         case 1: launch_k<1>(a, win, sn, grid, s); break;

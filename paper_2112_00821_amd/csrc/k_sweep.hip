@@ -7,8 +7,7 @@
 //
 // Tile 64 x 32 pixels, 256 threads = 4 waves; thread (tx, ty) owns column
 // tx and rows 8ty..8ty+7, so every LDS row read serves up to eight census
-// windows.  The warp of a thread's samples runs in phases (coordinates, all
-// gathers in flight, interpolation) so gather latency overlaps.  The label range of a block is the union of its pixels' windows
+// windows.  The label range of a block is the union of its pixels' windows
 // (dynamic cost volume); pixels whose window misses a label skip the store.
 // Warped values are double-buffered so one barrier per (label, view) pair
 // suffices.  Blocks are remapped so that neighbouring tiles share an XCD's L2.
@@ -39,70 +38,29 @@ __device__ __forceinline__ int combine_lr(int sL, int sR, int nL, int nR, int m)
     return best;
 }
 
-// Warp the region [rx0, rx0 + RW) x [ry0, ...) of the reference grid
-// (coordinates clamped to the image, so the halo replicates the border)
-// into LDS.  Same arithmetic as warp_sample, in three phases per thread:
-// all coordinates, then all gathers, then all interpolations.
+// Warp the tile region onto the reference grid into LDS.  tqx / tqy hold the
+// (clamped) pixel-centre coordinates of the region's columns and rows, so
+// the halo replicates the image border.
 template <int RW, int NS>
-__device__ __forceinline__ void warp_region(float *buf, const uint8_t *__restrict__ src, int w, int h, int rx0, int ry0,
-                                            int tid, double h0, double h1, double h2, double h3, double h4, double h5,
-                                            double h6, double h7, double h8) {
-    constexpr int NPT = (NS + NT - 1) / NT;
-    constexpr int WB = 4;   // samples per batch: 4 x 4 gathers in flight
+__device__ __forceinline__ void warp_region(float *buf, const uint8_t *__restrict__ src, int w, int h,
+                                            const double *tqx, const double *tqy, int tid, double h0, double h1,
+                                            double h2, double h3, double h4, double h5, double h6, double h7,
+                                            double h8) {
+    constexpr int NFULL = NS / NT;
     constexpr int DRY = NT / RW, DRX = NT % RW;
     int ry = tid / RW, rx = tid - (tid / RW) * RW;
-#pragma unroll 1
-    for (int i0 = 0; i0 < NPT; i0 += WB) {
-        float ax[WB], ay[WB];
-        uint32_t o00[WB], dxo[WB], dyo[WB];
-        uint32_t g[WB][4];
-#pragma unroll
-        for (int i = 0; i < WB; ++i) {
-            const double qx = (double)min(max(rx0 + rx, 0), w - 1) + 0.5;
-            const double qy = (double)min(max(ry0 + ry, 0), h - 1) + 0.5;
-            double hx = h0 * qx + h1 * qy + h2;
-            double hy = h3 * qx + h4 * qy + h5;
-            double hz = h6 * qx + h7 * qy + h8;
-            double inv = 1.0 / hz;
-            double sx = hz > 0.0 ? hx * inv - 0.5 : -1.0;
-            double sy = hz > 0.0 ? hy * inv - 0.5 : -1.0;
-            sx = fmin(fmax(sx, -1.0), (double)w);
-            sy = fmin(fmax(sy, -1.0), (double)h);
-            const double fx0 = floor(sx), fy0 = floor(sy);
-            const int x0 = (int)fx0, y0 = (int)fy0;
-            ax[i] = (float)(sx - fx0);
-            ay[i] = (float)(sy - fy0);
-            const int xa = min(max(x0, 0), w - 1), xb = min(max(x0 + 1, 0), w - 1);
-            const int ya = min(max(y0, 0), h - 1), yb = min(max(y0 + 1, 0), h - 1);
-            o00[i] = (uint32_t)(ya * w + xa);
-            dxo[i] = (uint32_t)(xb - xa);
-            dyo[i] = (uint32_t)((yb - ya) * w);
-            rx += DRX;
-            ry += DRY;
-            if (rx >= RW) {
-                rx -= RW;
-                ry += 1;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < WB; ++i) {
-            const bool act = i0 + i < NPT && tid + (i0 + i) * NT < NS;
-            const uint8_t *pa = src + o00[i];
-            g[i][0] = act ? pa[0] : 0u;
-            g[i][1] = act ? pa[dxo[i]] : 0u;
-            g[i][2] = act ? pa[dyo[i]] : 0u;
-            g[i][3] = act ? pa[dyo[i] + dxo[i]] : 0u;
-        }
-#pragma unroll
-        for (int i = 0; i < WB; ++i) {
-            if (i0 + i < NPT && tid + (i0 + i) * NT < NS) {
-                const float i00 = (float)g[i][0], i10 = (float)g[i][1], i01 = (float)g[i][2], i11 = (float)g[i][3];
-                const float top = i00 + ax[i] * (i10 - i00);
-                const float bot = i01 + ax[i] * (i11 - i01);
-                buf[tid + (i0 + i) * NT] = top + ay[i] * (bot - top);
-            }
+#pragma unroll 2
+    for (int i = 0; i < NFULL; ++i) {
+        buf[tid + i * NT] = warp_sample(src, w, h, h0, h1, h2, h3, h4, h5, h6, h7, h8, tqx[rx], tqy[ry]);
+        rx += DRX;
+        ry += DRY;
+        if (rx >= RW) {
+            rx -= RW;
+            ry += 1;
         }
     }
+    if (NS % NT != 0 && tid + NFULL * NT < NS)
+        buf[tid + NFULL * NT] = warp_sample(src, w, h, h0, h1, h2, h3, h4, h5, h6, h7, h8, tqx[rx], tqy[ry]);
 }
 }  // namespace
 
@@ -115,6 +73,7 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
     constexpr int NHI = NB > 32 ? NB - 32 : 0;
     constexpr int NS = RW * RH;
     __shared__ float wbuf[2][NS];
+    __shared__ double tqx[RW], tqy[RH];
     __shared__ int s_lo[kMaxFam], s_hi[kMaxFam];
 
     // XCD-aware remap: hardware dispatches workgroup b to XCD b % 8; give
@@ -137,6 +96,8 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
         s_lo[tid] = INT_MAX;
         s_hi[tid] = INT_MIN;
     }
+    if (tid < RW) tqx[tid] = (double)min(max(x0 - RX + tid, 0), a.w - 1) + 0.5;
+    if (tid < RH) tqy[tid] = (double)min(max(y0 - RY + tid, 0), a.h - 1) + 0.5;
     __syncthreads();
 
     uint32_t ref_hi[RPT], ref_lo[RPT];
@@ -203,7 +164,7 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
                 const double h0 = Hm[0], h1 = Hm[1], h2 = Hm[2], h3 = Hm[3], h4 = Hm[4], h5 = Hm[5], h6 = Hm[6],
                              h7 = Hm[7], h8 = Hm[8];
                 const uint8_t *src = a.views[k];
-                warp_region<RW, NS>(buf, src, a.w, a.h, x0 - RX, y0 - RY, tid, h0, h1, h2, h3, h4, h5, h6, h7, h8);
+                warp_region<RW, NS>(buf, src, a.w, a.h, tqx, tqy, tid, h0, h1, h2, h3, h4, h5, h6, h7, h8);
             }
             __syncthreads();
             // census of the warped view for this thread's four pixels
@@ -279,25 +240,22 @@ hipError_t launch_sweep(const SweepArgs &a0, hipStream_t s) {
         a.n_chunks = want < 1 ? 1 : (want > maxc ? maxc : want);
     }
     dim3 grid((unsigned)(tiles * a.n_chunks));
+#define FMVS_SWEEP_RW(CWv, CHv, R)                                                               \
+    if (a.warped)                                                                                \
+        hipLaunchKernelGGL((k_sweep<CWv, CHv, R, true>), grid, dim3(NT), 0, s, a);               \
+    else                                                                                         \
+        hipLaunchKernelGGL((k_sweep<CWv, CHv, R, false>), grid, dim3(NT), 0, s, a);
 #define FMVS_SWEEP(CWv, CHv)                                                                     \
     if (a.cw == CWv && a.ch == CHv) {                                                            \
-        if (rpt == 4) {                                                                          \
-            if (a.warped)                                                                        \
-                hipLaunchKernelGGL((k_sweep<CWv, CHv, 4, true>), grid, dim3(NT), 0, s, a);       \
-            else                                                                                 \
-                hipLaunchKernelGGL((k_sweep<CWv, CHv, 4, false>), grid, dim3(NT), 0, s, a);      \
-        } else {                                                                                 \
-            if (a.warped)                                                                        \
-                hipLaunchKernelGGL((k_sweep<CWv, CHv, 8, true>), grid, dim3(NT), 0, s, a);       \
-            else                                                                                 \
-                hipLaunchKernelGGL((k_sweep<CWv, CHv, 8, false>), grid, dim3(NT), 0, s, a);      \
-        }                                                                                        \
+        if (rpt == 4) { FMVS_SWEEP_RW(CWv, CHv, 4) }                                             \
+        else { FMVS_SWEEP_RW(CWv, CHv, 8) }                                                      \
         return hipGetLastError();                                                                \
     }
     FMVS_SWEEP(5, 5)
     FMVS_SWEEP(9, 7)
     FMVS_SWEEP(7, 7)
     FMVS_SWEEP(3, 3)
+#undef FMVS_SWEEP_RW
 #undef FMVS_SWEEP
     return hipErrorInvalidValue;
 }

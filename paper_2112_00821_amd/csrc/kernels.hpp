@@ -10,6 +10,7 @@ constexpr int kMaxViews = 8;
 constexpr int kMaxFam = 8;
 constexpr int kMaxLabels = 512;
 constexpr int kNumDirs = 8;
+constexpr int kMaxPgPlanes = 2048;   // plane-list entries held in LDS by the path-gradient SGM
 
 // Path directions r (step p -> p + r): (1,0) (-1,0) (0,1) (0,-1) (1,1)
 // (-1,-1) (1,-1) (-1,1); four-path SGM uses the first four.
@@ -58,6 +59,14 @@ struct SgmArgs {
     int dirs[8];
     uint16_t *out[8];         // [h][w][D] per launched direction (write mode)
     int path_begin[9];        // prefix sum of path counts over the launched directions
+    // path-gradient offsets (SGM^Pi-pg): level plane lists and geometry
+    int pg;
+    int sumG;
+    int goff[kMaxFam];
+    const double *delta;      // device, concatenated plane lists (sumG)
+    double fam_n[kMaxFam][3];
+    double Kinv[9];
+    double step[kMaxFam];
     // final mode: sum the finished directions' buffers, take the argmin
     int final_mode;
     int n_in;

@@ -209,7 +209,8 @@ void collect_timers(fassmvs_handle *h) {
     h->pending_timers.clear();
 }
 
-// Sweep tile height knob (FASSMVS_SWEEP_ROWS = 4 or 8 rows per thread).
+// Sweep tuning knob: FASSMVS_SWEEP_ROWS = 4 or 8 rows per thread (tile 64x16
+// or 64x32).  It changes the schedule only, never the result.
 int sweep_rows() {
     static int v = [] {
         const char *e = std::getenv("FASSMVS_SWEEP_ROWS");
@@ -217,6 +218,7 @@ int sweep_rows() {
     }();
     return v;
 }
+
 
 bool finite_all(const double *v, int n) {
     for (int i = 0; i < n; ++i)
@@ -292,7 +294,7 @@ fassmvs_status validate_config(const fassmvs_config *c, std::string &msg) {
                  (c->census_w == 7 && c->census_h == 7) || (c->census_w == 3 && c->census_h == 3);
     if (!ok_cw) { msg = "census window not built (3x3, 5x5, 7x7, 9x7)"; return FASSMVS_EUNSUPPORTED; }
     if (c->n_paths != 4 && c->n_paths != 8) { msg = "n_paths must be 4 or 8"; return FASSMVS_EINVAL; }
-    if (c->sgm_variant != 0 && c->sgm_variant != 1) { msg = "sgm_variant must be 0 or 1"; return FASSMVS_EINVAL; }
+    if (c->sgm_variant < 0 || c->sgm_variant > 2) { msg = "sgm_variant must be 0, 1 or 2"; return FASSMVS_EINVAL; }
     if (c->p1 < 0 || c->p1 > 4096) { msg = "p1 out of range"; return FASSMVS_EINVAL; }
     if (c->p2_mode != 0 && c->p2_mode != 1) { msg = "p2_mode must be 0 or 1"; return FASSMVS_EINVAL; }
     if (c->p2_mode == 0 && (c->p2_fixed < c->p1 || c->p2_fixed > 65535)) {
@@ -497,11 +499,28 @@ fassmvs_status alloc_frame(fassmvs_handle *h, const FramePlan &P) {
 // buffer in one launch (all paths of all directions concurrently), then a
 // streaming kernel sums the buffers and takes the argmin.  With Sbar the
 // full aggregate is also written (tests).
+struct PgGeom {
+    const double *delta;   // device plane lists of the level
+    const double (*fam_n)[3];
+};
+
 fassmvs_status run_sgm(fassmvs_handle *h, const LevelPlan &L, const uint8_t *S, const int32_t *offs,
                        const int8_t *dI, const uint8_t *ref, int p1, const int *lut, int n_paths, uint16_t *const *bufs,
-                       uint16_t *Sbar, uint16_t *wta, uint16_t *c3) {
+                       uint16_t *Sbar, uint16_t *wta, uint16_t *c3, const PgGeom *pgg = nullptr) {
     SgmArgs a;
     std::memset(&a, 0, sizeof(a));
+    if (pgg) {
+        if (L.sumG > kMaxPgPlanes) return fail(h, FASSMVS_EUNSUPPORTED, "path-gradient SGM holds at most 2048 planes");
+        a.pg = 1;
+        a.sumG = L.sumG;
+        a.delta = pgg->delta;
+        for (int f = 0; f < L.F; ++f) {
+            a.goff[f] = L.goff[f];
+            a.step[f] = L.step[f];
+            for (int i = 0; i < 3; ++i) a.fam_n[f][i] = pgg->fam_n[f][i];
+        }
+        std::memcpy(a.Kinv, L.Kinv, sizeof(a.Kinv));
+    }
     a.w = L.w;
     a.h = L.h;
     a.D = L.D;
@@ -615,9 +634,10 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
         }
         uint16_t *bufs[8];
         for (int i = 0; i < 8; ++i) bufs[i] = (uint16_t *)h->sgmbuf[i].p;
+        PgGeom pgg{dblob + L.d_off, P.fam_n};
         fassmvs_status st = run_sgm(h, L, (const uint8_t *)h->S.p, offs, dI, ref, P.p1, P.lut, c.n_paths, bufs,
                                     c.sgm_debug ? (uint16_t *)h->sbar.p : nullptr, (uint16_t *)h->wta.p,
-                                    (uint16_t *)h->c3.p);
+                                    (uint16_t *)h->c3.p, c.sgm_variant == 2 ? &pgg : nullptr);
         if (st != FASSMVS_OK) return st;
         {
             Timer t(h, ST_REFINE);
@@ -1179,6 +1199,59 @@ fassmvs_status fassmvs_stage_sgm(fassmvs_handle *h, int32_t w, int32_t hgt, int3
         }
     }
     st = run_sgm(h, L, S, offs, dI, ref, p1, lut, n_paths, bufs, Sbar, wta, c3);
+    if (st != FASSMVS_OK) return st;
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_stage_sgm_pg(fassmvs_handle *h, int32_t w, int32_t hgt, int32_t n_fam, const int32_t *W,
+                                    const int32_t *G, const uint8_t *S, const int32_t *offs, const uint8_t *ref,
+                                    int32_t p1, const int32_t *lut, int32_t n_paths, const double *fam_delta,
+                                    const double *fam_n, const double *Kinv, const double *step, uint16_t *Lr,
+                                    uint16_t *Sbar, uint16_t *wta, uint16_t *c3) {
+    STAGE_BEGIN;
+    if (!W || !G || !S || !ref || !lut || !fam_delta || !fam_n || !Kinv || !step || w < 1 || hgt < 1 || n_fam < 1 ||
+        n_fam > kMaxFam)
+        return fail(h, FASSMVS_EINVAL, "bad sgm arguments");
+    if (n_paths != 4 && n_paths != 8) return fail(h, FASSMVS_EINVAL, "n_paths must be 4 or 8");
+    if ((wta == nullptr) != (c3 == nullptr)) return fail(h, FASSMVS_EINVAL, "wta and c3 go together");
+    LevelPlan L;
+    L.w = w;
+    L.h = hgt;
+    L.F = n_fam;
+    L.D = 0;
+    L.sumG = 0;
+    for (int f = 0; f < n_fam; ++f) {
+        if (W[f] < 1 || W[f] > G[f] || (!offs && W[f] != G[f])) return fail(h, FASSMVS_EINVAL, "bad family sizes");
+        L.W[f] = W[f];
+        L.G[f] = G[f];
+        L.foff[f] = L.D;
+        L.goff[f] = L.sumG;
+        L.step[f] = step[f];
+        L.D += W[f];
+        L.sumG += G[f];
+    }
+    std::memcpy(L.Kinv, Kinv, 72);
+    if (L.D > kMaxLabels) return fail(h, FASSMVS_EUNSUPPORTED, "too many labels");
+    for (int i = 0; i < 256; ++i)
+        if (lut[i] < p1) return fail(h, FASSMVS_EINVAL, "P2 must be >= P1");
+    fassmvs_status st = ensure(h, h->params, (size_t)L.sumG * 8);
+    if (st != FASSMVS_OK) return st;
+    HIPCHK(h, hipMemcpyAsync(h->params.p, fam_delta, (size_t)L.sumG * 8, hipMemcpyHostToDevice, h->stream), "delta");
+    double fn[kMaxFam][3];
+    for (int f = 0; f < n_fam; ++f)
+        for (int i = 0; i < 3; ++i) fn[f][i] = fam_n[3 * f + i];
+    PgGeom pgg{(const double *)h->params.p, fn};
+    const size_t ND = (size_t)w * hgt * L.D;
+    uint16_t *bufs[8];
+    if (Lr) {
+        for (int d = 0; d < n_paths; ++d) bufs[d] = Lr + (size_t)d * ND;
+    } else {
+        for (int d = 0; d < n_paths; ++d) {
+            if ((st = ensure(h, h->sgmbuf[d], ND * 2)) != FASSMVS_OK) return st;
+            bufs[d] = (uint16_t *)h->sgmbuf[d].p;
+        }
+    }
+    st = run_sgm(h, L, S, offs, nullptr, ref, p1, lut, n_paths, bufs, Sbar, wta, c3, &pgg);
     if (st != FASSMVS_OK) return st;
     STAGE_END;
 }

@@ -551,5 +551,38 @@ WORKLOADS = {
 }
 
 
-def make_workload(name: str):
-    return WORKLOADS[name]()
+def make_workload(name: str, cache_dir: str | None = None):
+    """Render a named workload.  With cache_dir (or FASSMVS_SCENE_CACHE) the
+    rendered bundle (images, poses, intrinsics, families, parameters, ground
+    truth) is kept in a pickle-free .npz and reused."""
+    import json
+    import os
+    cache_dir = cache_dir or os.environ.get("FASSMVS_SCENE_CACHE")
+    if not cache_dir:
+        return WORKLOADS[name]()
+    path = os.path.join(cache_dir, f"{name}.npz")
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        nv = int(z["n_views"])
+        fams = json.loads(str(z["families"]))
+        wl = dict(name=name, K=z["K"], width=int(z["width"]), height=int(z["height"]),
+                  ref=dict(img=z["ref"], R=z["R_ref"], t=z["t_ref"]),
+                  views=[dict(img=z[f"view{i}"], R=z["R_views"][i], t=z["t_views"][i]) for i in range(nv)],
+                  side=[int(v) for v in z["side"]], families=fams, params=json.loads(str(z["params"])),
+                  gt=dict(depth=z["depth"], normal=z["normal"], surf=z["surf"]), scene=None)
+        return wl
+    wl = WORKLOADS[name]()
+    os.makedirs(cache_dir, exist_ok=True)
+    arrs = {"ref": wl["ref"]["img"], "R_ref": np.asarray(wl["ref"]["R"]), "t_ref": np.asarray(wl["ref"]["t"]),
+            "R_views": np.array([v["R"] for v in wl["views"]]), "t_views": np.array([v["t"] for v in wl["views"]]),
+            "n_views": np.array(len(wl["views"])), "side": np.array(wl["side"]), "K": np.asarray(wl["K"]),
+            "width": np.array(wl["width"]), "height": np.array(wl["height"]),
+            "families": np.array(json.dumps([dict(f, n=[float(x) for x in f["n"]]) for f in wl["families"]])),
+            "params": np.array(json.dumps(wl["params"])),
+            "depth": wl["gt"]["depth"], "normal": wl["gt"]["normal"], "surf": wl["gt"]["surf"]}
+    for i, v in enumerate(wl["views"]):
+        arrs[f"view{i}"] = v["img"]
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **arrs)
+    os.replace(tmp, path)
+    return wl

@@ -58,6 +58,18 @@ def test_frame_matches_oracle(orc, fm, name):
         print(name, "label agreement per level", rep)
 
 
+@pytest.mark.parametrize("name", ["config2_small", "config3_small"])
+def test_frame_path_gradient_matches_oracle(orc, fm, name):
+    import copy
+    wl = copy.deepcopy(scenegen.make_workload(name))
+    wl["params"]["sgm_variant"] = 2
+    ref = orc.run_frame(wl, keep=True)
+    cfg = fm.config_from_params(wl["params"], keep_levels=1)
+    with fm.Handle(cfg) as h:
+        h.run_frame(wl)
+        _compare(ref, h, wl, range(wl["params"]["n_levels"]))
+
+
 def test_frame_device_inputs_and_outputs(orc, fm):
     wl = scenegen.make_workload("config1")
     cfg = fm.config_from_params(wl["params"])

@@ -226,3 +226,25 @@ def test_seed_bit_exact(orc, hd):
     assert np.array_equal(nbar.numpy(), seed["nbar"])
     assert np.array_equal(offs.numpy(), seed["offs"])
     assert np.mean(dI.numpy() == seed["dI"]) >= 0.9999
+
+
+@pytest.mark.parametrize("name,level", [("config2_small", 1), ("config3_small", 1), ("config1", 0)])
+def test_sgm_path_gradient_bit_exact(orc, hd, name, level):
+    """SGM^Pi-pg: path costs and aggregate bit-exact with the oracle's
+    path-gradient recursion (windows and plane families included)."""
+    wl = scenegen.make_workload(name)
+    out = orc.run_frame(wl, keep=True, levels_only=level)
+    lv = out["levels"][level]
+    plan = lv["plan"]
+    Ki, _ = orc.kinv_level(np.asarray(wl["K"]), level)
+    p1, lut = _lut(orc, wl)
+    fam_delta = np.concatenate(plan["deltas"])
+    geom = dict(G=plan["G"], fam_delta=fam_delta, fam_n=plan["fam_n"], Kinv=Ki, step=plan["step"])
+    Sbar, Lr = orc.sgm(lv["S"], plan["W"], p1, lut, lv["img"], 8, offs=lv["offs"], want_lr=True, pg=geom)
+    r = hd.stage_sgm_pg(hd.upload(lv["S"]), plan["W"], plan["G"], p1, lut, hd.upload(lv["img"]), 8, fam_delta,
+                        plan["fam_n"], Ki, plan["step"],
+                        offs=hd.upload(lv["offs"]) if lv["offs"] is not None else None, want_lr=True,
+                        want_sbar=True)
+    assert np.array_equal(r["Lr"].numpy(), Lr)
+    assert np.array_equal(r["Sbar"].numpy(), Sbar)
+    assert np.array_equal(r["wta"].numpy(), np.argmin(Sbar, axis=-1))

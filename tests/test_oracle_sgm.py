@@ -244,3 +244,58 @@ def test_refinement_matches_parabola_vertex(orc):
         a, b, _ = np.polyfit(d3, c3, 2)
         assert a > 0
         assert depth[0, 0] == pytest.approx(min(max(-b / (2 * a), d3[0]), d3[2]), rel=1e-6)
+
+
+# --------------------------------------------------------------------------
+# path-gradient variant
+# --------------------------------------------------------------------------
+
+def _fronto_geom(orc, G, w):
+    K = np.array([[300.0, 0, w / 2.0], [0, 300.0, 0.5], [0, 0, 1]])
+    Ki, _ = orc.kinv_level(K, 0)
+    deltas = orc.plane_list(20.0, 400.0, G)
+    step = (1 / 20.0 - 1 / 400.0) / (G - 1)
+    return dict(G=[G], fam_delta=deltas, fam_n=np.array([[0, 0, -1.0]]), Kinv=Ki, step=np.array([step]))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pg_fronto_offsets_continue_the_label_slope(orc, seed):
+    """For fronto-parallel planes inverse depth is affine in the plane index,
+    so the path-gradient extrapolation reduces exactly to continuing the
+    previous step's label change: di_pg(p) = g(q2) - g(q) (clamped to 7)."""
+    rng = np.random.default_rng(200 + seed)
+    n, D = int(rng.integers(5, 30)), int(rng.integers(4, 20))
+    S = rng.integers(0, 60, (1, n, D)).astype(np.uint8)
+    p1 = int(rng.integers(1, 10))
+    lut = np.full(256, p1 + int(rng.integers(0, 40)), np.int32)
+    ref = rng.integers(0, 256, (1, n)).astype(np.uint8)
+    geom = _fronto_geom(orc, D, n)
+    _, Lr = orc.sgm(S, [D], p1, lut, ref, 4, want_sbar=False, want_lr=True, pg=geom)
+    got = Lr[0, 0].astype(np.int64)            # direction (1, 0) along the row
+    L = np.zeros((n, D), np.int64)
+    L[0] = S[0, 0]
+    arg = [int(np.argmin(L[0]))]
+    for t in range(1, n):
+        di = 0 if t < 2 else int(np.clip(arg[t - 2] - arg[t - 1], -7, 7))
+        M = L[t - 1].min()
+        for i in range(D):
+            best = M + lut[0]
+            for e in (-1, 0, 1):
+                j = i + di + e
+                if 0 <= j < D:
+                    best = min(best, L[t - 1, j] + (0 if e == 0 else p1))
+            L[t, i] = S[0, t, i] + best - M
+        arg.append(int(np.argmin(L[t])))
+    assert np.array_equal(got, L)
+
+
+def test_pg_constant_winner_equals_plain(orc):
+    rng = np.random.default_rng(9)
+    S = rng.integers(40, 90, (9, 11, 12)).astype(np.uint8)
+    S[..., 5] = 0
+    ref = rng.integers(0, 256, (9, 11)).astype(np.uint8)
+    lut = orc.p2_lut(8, 1, 0, 8.0, 10.0)
+    geom = _fronto_geom(orc, 12, 11)
+    a, _ = orc.sgm(S, [12], 8, lut, ref, 8)
+    b, _ = orc.sgm(S, [12], 8, lut, ref, 8, pg=geom)
+    assert np.array_equal(a, b)
