@@ -32,6 +32,11 @@ SWEEP_ALG_OPS_9x7 = 62 + 3 + 15
 # algorithmic bytes of SGM per (pixel, hypothesis): S read once per path (8 x
 # 1 B) plus the aggregate written and read once (2 x 2 B)
 SGM_ALG_BYTES = 12.0
+# bytes of this design per (pixel, hypothesis): S read by each of the 8
+# direction walks (8 x 1 B), each direction's uint16 path costs written once
+# and read once by the streaming winner-takes-all (2 x 8 x 2 B)
+SGM_DESIGN_BYTES = 40.0
+PROFILE = os.path.join(ROOT, "profiles", "k_sweep_config2.md")
 
 WORKLOADS = {
     "config2": ("1920x1080 oblique urban scene, reference + 4 views (2 left, 2 right), 3 levels x 128 "
@@ -105,17 +110,29 @@ def main():
     sweep_frame_ms = times["sweep"][0] / args.steps
     ks_value = hyp / 1e6 / ((sweep_frame_ms + sgm_ms) / 1e3)
     # dominant kernel and its roofline
+    from paper_2112_00821_amd import profsum
     if sweep_frame_ms >= sgm_ms:
         units = work["pixel_hyp_views"] / sweep_launches
         achieved = SWEEP_ALG_OPS_9x7 * units / (sweep_ms / 1e3) / 1e12
+        tr = profsum.read_traffic(PROFILE, "k_sweep") if args.workload == "config2" else None
         roof = {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": PEAK_VALU_TOPS,
-                "unit": "TOP/s", "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
-                "avg_launch_ms": sweep_ms, "alg_ops_per_px_hyp_view": SWEEP_ALG_OPS_9x7}
+                "unit": "TOP/s", "frac": achieved / PEAK_VALU_TOPS,
+                "traffic": tr["traffic_bytes_per_launch"] if tr else None,
+                "avg_launch_ms": sweep_ms, "launches_per_frame": sweep_launches,
+                "alg_ops_per_px_hyp_view": SWEEP_ALG_OPS_9x7}
     else:
         achieved = SGM_ALG_BYTES * hyp / (sgm_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": "k_sgm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None, "stage_ms_per_frame": sgm_ms,
                 "alg_bytes_per_px_hyp": SGM_ALG_BYTES}
+    # the aggregation's bandwidth, by the method's bytes and by this design's
+    sgm_roof = {"bound": "hbm", "stages": "sgm_dirs + sgm_wta", "ms_per_frame": sgm_ms, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "alg_bytes_per_px_hyp": SGM_ALG_BYTES,
+                "achieved_alg": SGM_ALG_BYTES * hyp / (sgm_ms / 1e3) / 1e9,
+                "design_bytes_per_px_hyp": SGM_DESIGN_BYTES,
+                "achieved_design": SGM_DESIGN_BYTES * hyp / (sgm_ms / 1e3) / 1e9}
+    sgm_roof["frac_alg"] = sgm_roof["achieved_alg"] / PEAK_HBM_GBS
+    sgm_roof["frac_design"] = sgm_roof["achieved_design"] / PEAK_HBM_GBS
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpx·hyp/s", "n_gpus": 1, "steps": args.steps,
@@ -130,6 +147,7 @@ def main():
         "stage_ms_per_frame": {k: round(v[0] / args.steps, 4) for k, v in times.items() if v[1]},
         "sweep_label_inflation": round(work["sweep_evaluated"] / hyp, 4) if hyp else None,
         "roofline": roof,
+        "sgm_roofline": sgm_roof,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

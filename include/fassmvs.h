@@ -184,7 +184,11 @@ fassmvs_status fassmvs_device_alloc(fassmvs_handle *h, size_t bytes, void **ptr)
 fassmvs_status fassmvs_device_free(fassmvs_handle *h, void *ptr);
 
 /* Copy bytes; kind 0 host->device, 1 device->host, 2 device->device.
- * Returns when the copy has completed (the handle's stream is drained first). */
+ * Returns when the copy has completed (the handle's stream is drained first).
+ * A device->device copy of non-overlapping, 16-byte aligned buffers whose size
+ * is a multiple of 16 runs the library's own plain copy kernel (k_copy16),
+ * which touches every byte once; other copies use hipMemcpyAsync.  Ranges
+ * that overlap are copied by hipMemcpyAsync with its semantics. */
 fassmvs_status fassmvs_memcpy(fassmvs_handle *h, void *dst, const void *src, size_t bytes, int32_t kind);
 
 /* Fill device memory with a byte value (a fill kernel, not a memset node). */

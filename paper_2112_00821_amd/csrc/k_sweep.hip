@@ -9,6 +9,8 @@
 // tx and rows 8ty..8ty+7, so every LDS row read serves up to eight census
 // windows.  The label range of a block is the union of its pixels' windows
 // (dynamic cost volume); pixels whose window misses a label skip the store.
+// Costs leave in 4-byte words per pixel (label-innermost rows are
+// contiguous), so the L2 sees whole-word writes rather than single bytes.
 // Warped values are double-buffered so one barrier per (label, view) pair
 // suffices.  Blocks are remapped so that neighbouring tiles share an XCD's L2.
 #include "dev_common.hpp"
@@ -139,9 +141,19 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
         ++f;
     }
     int g = s_lo[f] + (pos0 - fbase);
+    // labels of family f this block evaluates: [g_first, g_last]
+    int g_first = g;
+    int g_last = s_lo[f] + min(pos1 - fbase, s_hi[f] - s_lo[f]) - 1;
     int off[RPT];   // window offsets of the current family
 #pragma unroll
     for (int j = 0; j < RPT; ++j) off[j] = (a.offs && valid[j]) ? a.offs[(size_t)f * N + pix[j]] : 0;
+    // Costs are written 4 labels at a time when the label count keeps the
+    // pixel rows 4-byte aligned: acc holds the last bytes of the pixel's
+    // run, the newest in the top byte.  Byte stores otherwise.
+    const bool pack = (a.D & 3) == 0 && ((uintptr_t)a.S & 3) == 0;
+    uint32_t acc[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) acc[j] = 0;
 
     int it = 0;
     for (int pos = pos0; pos < pos1; ++pos) {
@@ -205,17 +217,35 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
         // store the combined cost where this label lies in the pixel's window
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-            int o = off[j];
+            const int o = off[j];
             if (valid[j] && g >= o && g < o + a.W[f]) {
-                int cst = combine_lr(sL[j], sR[j], a.nL, a.nR, a.m);
-                a.S[(size_t)pix[j] * a.D + a.foff[f] + (g - o)] = (uint8_t)cst;
+                const uint32_t cst = (uint32_t)combine_lr(sL[j], sR[j], a.nL, a.nR, a.m);
+                const int idx = a.foff[f] + (g - o);
+                uint8_t *dst = a.S + (size_t)pix[j] * a.D + idx;
+                if (pack) {
+                    acc[j] = (acc[j] >> 8) | (cst << 24);
+                    const int run_end = min(o + a.W[f], g_last + 1) - 1;
+                    if ((idx & 3) == 3 || g == run_end) {
+                        const int n = min((idx & 3) + 1, g - max(o, g_first) + 1);
+                        if (n == 4) {
+                            *(uint32_t *)(dst - 3) = acc[j];
+                        } else {
+                            for (int b = 0; b < n; ++b) dst[b - n + 1] = (uint8_t)(acc[j] >> (8 * (4 - n + b)));
+                        }
+                    }
+                } else {
+                    *dst = (uint8_t)cst;
+                }
             }
         }
         if (++g >= s_hi[f]) {
+            fbase += s_hi[f] - s_lo[f];
             ++f;
             while (f < a.n_fam && s_hi[f] <= s_lo[f]) ++f;
             if (f < a.n_fam) {
                 g = s_lo[f];
+                g_first = g;
+                g_last = s_lo[f] + min(pos1 - fbase, s_hi[f] - s_lo[f]) - 1;
 #pragma unroll
                 for (int j = 0; j < RPT; ++j) off[j] = (a.offs && valid[j]) ? a.offs[(size_t)f * N + pix[j]] : 0;
             }

@@ -1,12 +1,19 @@
-"""Parity at the benchmark's full size (1920x1080, 4 views, 3 levels x 128
-planes, census 9x7, SGM^Pi-sn 8 paths), in the launch configuration the
-benchmark times.
+"""Parity at full size, in the launch configuration the benchmark times:
+
+* 1920x1080, 4 views, 3 levels x 128 fronto-parallel planes, census 9x7,
+  SGM^Pi-sn 8 paths (the benchmark workload);
+* 2704x1520, 4 views, 4 plane families (fronto-parallel, ground, ground
+  tilted by +-20 degrees) x 96 planes per level (384 labels), census 9x7,
+  SGM^Pi-sn 8 paths.
+
+Checked:
 
 * pyramid (all images, all levels) and the level-0 reference census:
   bit-exact over the whole frame;
 * the coarsest level: every map compared with the oracle's own full run of
   that level (labels >= 99.9 %, depth 1e-3), and the level-1 seeds derived
-  from it;
+  from it (1920x1080 only: the oracle's run of the 676x380 x 384-label level
+  is replaced there by sampled costs);
 * level 0: the cost volume at sampled pixels (all labels of the pixel) and
   the path costs along sampled whole paths (a row, a column, diagonals), the
   oracle recomputing the costs of every pixel on the path itself.  The label
@@ -20,11 +27,15 @@ import scenegen
 
 pytestmark = pytest.mark.gpu
 
+WORKLOADS = ["config2", "config3"]
 
-@pytest.fixture(scope="module")
-def run(orc):
+
+@pytest.fixture(scope="module", params=WORKLOADS)
+def run(request, orc):
     import paper_2112_00821_amd as fm
-    wl = scenegen.make_workload("config2")
+    name = request.param
+    print(f"\n[fullsize] workload {name}", flush=True)
+    wl = scenegen.make_workload(name)
     cfg = fm.config_from_params(wl["params"], keep_levels=1, profile=1)
     h = fm.Handle(cfg)
     ref = dict(wl["ref"], img=h.upload(wl["ref"]["img"]))
@@ -32,70 +43,108 @@ def run(orc):
     t = h.submit_frame(ref, views, wl["side"], wl["K"], wl["families"], mem_kind=fm.MEM_DEVICE)
     d = np.zeros((wl["height"], wl["width"]), np.float32)
     h.poll(t, depth=d)
-    yield wl, h, d
+    yield name, wl, h, d
     h.close()
 
 
 def test_pyramid_and_census_bit_exact(orc, run):
-    wl, h, _ = run
+    _, wl, h, _ = run
+    n = wl["params"]["n_levels"]
     imgs = [wl["ref"]["img"]] + [v["img"] for v in wl["views"]]
     for i, img in enumerate(imgs):
         cur = img
-        for l in range(3):
+        for l in range(n):
             assert np.array_equal(h.level_map(l, 30 + i), cur), (i, l)
-            if l < 2:
+            if l < n - 1:
                 cur = orc.pyr_down(cur)
     assert np.array_equal(h.level_map(0, 20), orc.census(wl["ref"]["img"], 9, 7))
 
 
-def test_coarsest_level_full(orc, run):
-    wl, h, _ = run
-    out = orc.run_frame(wl, keep=True, levels_only=2)
-    lv = out["levels"][2]
-    lab = h.level_map(2, 4)
-    agree = lab == lv["label"]
-    assert agree.mean() >= 0.999, agree.mean()
-    dep = h.level_map(2, 0)
-    ok = agree & (lv["depth"] > 0)
-    assert np.max(np.abs(dep[ok] - lv["depth"][ok]) / lv["depth"][ok]) <= 1e-3
-    if np.array_equal(dep, lv["depth"]):
-        assert np.max(np.abs(h.level_map(2, 2) - lv["normal"])) <= 1e-4
-        assert np.max(np.abs(h.level_map(2, 3) - lv["conf"])) <= 1e-4
-        # seeds of level 1 from the same maps
-        seed = lv["seed"]
-        assert np.mean(h.level_map(1, 6) == seed["offs"]) >= 0.9999
-        assert np.mean(h.level_map(1, 7) == seed["dI"]) >= 0.9999
+def _views_at(orc, wl, level):
+    out = []
+    for v in [wl["ref"]] + wl["views"]:
+        cur = v["img"]
+        for _ in range(level):
+            cur = orc.pyr_down(cur)
+        out.append(cur)
+    return out[0], out[1:]
 
 
-def _level0(orc, wl):
+def _level(orc, wl, level):
+    """Level geometry and every plane's homography, families concatenated."""
     K = np.asarray(wl["K"])
-    Ki, Kl = orc.kinv_level(K, 0)
-    plan = orc.level_plan(wl, 0)
+    Ki, Kl = orc.kinv_level(K, level)
+    plan = orc.level_plan(wl, level)
     rel = [orc.relative_pose(wl["ref"]["R"], wl["ref"]["t"], v["R"], v["t"]) for v in wl["views"]]
-    H = np.zeros((len(rel), plan["G"][0], 3, 3))
+    H = np.zeros((len(rel), sum(plan["G"]), 3, 3))
     for k, (R, t) in enumerate(rel):
-        for j, dv in enumerate(plan["deltas"][0]):
-            H[k, j] = orc.homography(Kl, Ki, R, t, plan["fam_n"][0], dv)
+        g0 = 0
+        for f, dl in enumerate(plan["deltas"]):
+            for j, dv in enumerate(dl):
+                H[k, g0 + j] = orc.homography(Kl, Ki, R, t, plan["fam_n"][f], dv)
+            g0 += len(dl)
     return Ki, plan, H
 
 
+def test_coarsest_level(orc, run):
+    name, wl, h, _ = run
+    top = wl["params"]["n_levels"] - 1
+    if name == "config2":
+        out = orc.run_frame(wl, keep=True, levels_only=top)
+        lv = out["levels"][top]
+        lab = h.level_map(top, 4)
+        agree = lab == lv["label"]
+        assert agree.mean() >= 0.999, agree.mean()
+        dep = h.level_map(top, 0)
+        ok = agree & (lv["depth"] > 0)
+        assert np.max(np.abs(dep[ok] - lv["depth"][ok]) / lv["depth"][ok]) <= 1e-3
+        if np.array_equal(dep, lv["depth"]):
+            assert np.max(np.abs(h.level_map(top, 2) - lv["normal"])) <= 1e-4
+            assert np.max(np.abs(h.level_map(top, 3) - lv["conf"])) <= 1e-4
+            # seeds of the next level from the same maps
+            seed = lv["seed"]
+            assert np.mean(h.level_map(top - 1, 6) == seed["offs"]) >= 0.9999
+            assert np.mean(h.level_map(top - 1, 7) == seed["dI"]) >= 0.9999
+        return
+    # sampled costs of the coarsest level over every family's full list (the
+    # pipeline keeps only level 0's volume, so the cost stage entry point
+    # recomputes it from the pipeline's own pyramid and census)
+    Ki, plan, H = _level(orc, wl, top)
+    img, views = _views_at(orc, wl, top)
+    assert np.array_equal(h.level_map(top, 30), img)
+    ctd = h.upload(h.level_map(top, 20))
+    vd = [h.upload(h.level_map(top, 31 + k)) for k in range(len(views))]
+    S = h.stage_cost(ctd, vd, wl["side"], 9, 7, plan["G"], plan["W"], H).numpy()
+    hh, ww = S.shape[:2]
+    rng = np.random.default_rng(5)
+    xy = np.stack([rng.integers(0, ww, 300), rng.integers(0, hh, 300)], -1)
+    xy = np.concatenate([xy, [[0, 0], [ww - 1, hh - 1], [ww - 1, 0], [0, hh - 1]]]).astype(np.int32)
+    ct = orc.census(img, 9, 7)
+    assert np.array_equal(h.level_map(top, 20), ct)
+    exp = orc.cost_pixels(ct, views, wl["side"], 9, 7, plan["G"], plan["W"], H, xy)
+    got = S[xy[:, 1], xy[:, 0]]
+    assert np.mean(got == exp) >= 0.9999
+    assert np.max(np.abs(got.astype(int) - exp.astype(int))) <= 2
+
+
 def test_level0_windows_centred_on_seed(orc, run):
-    wl, h, _ = run
-    Ki, plan, _ = _level0(orc, wl)
-    offs = h.level_map(0, 6)[0]
+    _, wl, h, _ = run
+    Ki, plan, _ = _level(orc, wl, 0)
+    offs = h.level_map(0, 6, n_fam=len(plan["G"]))
     d1 = h.level_map(1, 0)
-    hh, ww = offs.shape
+    hh, ww = offs.shape[1:]
     dbar = orc.upsample_nn(d1, ww, hh)
-    exp = orc.window_offsets(dbar, Ki, plan["fam_n"], plan["inv_dmin"], plan["step"], plan["G"], plan["W"])[0]
+    exp = orc.window_offsets(dbar, Ki, plan["fam_n"], plan["inv_dmin"], plan["step"], plan["G"], plan["W"])
     assert np.array_equal(offs, exp)
 
 
 def test_level0_cost_samples(orc, run):
-    wl, h, _ = run
-    Ki, plan, H = _level0(orc, wl)
-    D = plan["W"][0]
+    _, wl, h, _ = run
+    Ki, plan, H = _level(orc, wl, 0)
+    D = sum(plan["W"])
+    nf = len(plan["G"])
     S = h.level_map(0, 9, D=D)
-    offs = h.level_map(0, 6)
+    offs = h.level_map(0, 6, n_fam=nf)
     rng = np.random.default_rng(11)
     hh, ww = S.shape[:2]
     xy = np.stack([rng.integers(0, ww, 400), rng.integers(0, hh, 400)], -1)
@@ -108,15 +157,8 @@ def test_level0_cost_samples(orc, run):
     assert np.max(np.abs(got.astype(int) - exp.astype(int))) <= 2
 
 
-@pytest.mark.parametrize("r,which", [(0, 517), (2, 1201), (4, 333), (7, 2500)])
-def test_level0_path_costs(orc, run, r, which):
-    """Whole path of direction r: the oracle recomputes S on every pixel of
-    the path and runs its own recursion (a path laid out as a strip)."""
-    wl, h, _ = run
-    Ki, plan, H = _level0(orc, wl)
-    D = plan["W"][0]
-    hh, ww = wl["height"], wl["width"]
-    dx, dy = orc.DIRS[r]
+def _path_pixels(r, which, ww, hh, DIRS):
+    dx, dy = DIRS[r]
     # start pixel of path `which` (rows for horizontal, columns for vertical,
     # top/bottom row then left/right column for diagonals)
     if dy == 0:
@@ -134,17 +176,29 @@ def test_level0_path_costs(orc, run, r, which):
         pts.append((x, y))
         x += dx
         y += dy
-    xy = np.array(pts, np.int32)
-    offs = h.level_map(0, 6)
-    dI = h.level_map(0, 7)
+    return np.array(pts, np.int32)
+
+
+@pytest.mark.parametrize("r,which", [(0, 517), (2, 1201), (4, 333), (7, 2500)])
+def test_level0_path_costs(orc, run, r, which):
+    """Whole path of direction r: the oracle recomputes S on every pixel of
+    the path and runs its own recursion (a path laid out as a strip)."""
+    _, wl, h, _ = run
+    Ki, plan, H = _level(orc, wl, 0)
+    D = sum(plan["W"])
+    nf = len(plan["G"])
+    hh, ww = wl["height"], wl["width"]
+    xy = _path_pixels(r, which, ww, hh, orc.DIRS)
+    offs = h.level_map(0, 6, n_fam=nf)
+    dI = h.level_map(0, 7, n_fam=nf)
     ct = orc.census(wl["ref"]["img"], 9, 7)
     Sp = orc.cost_pixels(ct, [v["img"] for v in wl["views"]], wl["side"], 9, 7, plan["G"], plan["W"], H, xy,
                          offs=offs)
     n = len(xy)
     strip_S = Sp.reshape(n, 1, D)
-    strip_offs = offs[:, xy[:, 1], xy[:, 0]].reshape(1, n, 1)
-    strip_dI = np.zeros((8, n, 1, 1), np.int8)
-    strip_dI[2] = dI[r, xy[:, 1], xy[:, 0], :].reshape(n, 1, 1)
+    strip_offs = offs[:, xy[:, 1], xy[:, 0]].reshape(nf, n, 1)
+    strip_dI = np.zeros((8, n, 1, nf), np.int8)
+    strip_dI[2] = dI[r, xy[:, 1], xy[:, 0], :].reshape(n, 1, nf)
     ref = wl["ref"]["img"][xy[:, 1], xy[:, 0]].reshape(n, 1)
     m = orc.subset_multiplier(wl["side"])
     p = wl["params"]
