@@ -53,6 +53,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--host-io-steps", type=int, default=5,
+                    help="after the timed region, run this many frames with host input/output buffers and report "
+                         "that PCIe-inclusive rate beside the device-resident one")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device once (a plain copy kernel of known "
                          "size whose HBM byte counters calibrate the profiler's FETCH_SIZE / WRITE_SIZE)")
@@ -101,6 +104,20 @@ def main():
         times = hd.stage_times()
         work = hd.frame_work()
 
+        # the same frames handed over as host buffers (PCIe upload of the
+        # five images and download of the three output maps included)
+        host_ms = None
+        if args.host_io_steps:
+            dh = np.zeros((h, w), np.float32)
+            nh = np.zeros((h, w, 3), np.float32)
+            ch = np.zeros((h, w), np.float32)
+            hd.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.host_io_steps):
+                t = hd.submit_frame(wl["ref"], wl["views"], wl["side"], wl["K"], wl["families"])
+                hd.poll(t, dh, nh, ch, wait_ms=-1)
+            host_ms = (time.perf_counter() - t1) / args.host_io_steps * 1e3
+
     ms = el / args.steps * 1e3
     hyp = work["pixel_hyp"]
     value = hyp / 1e6 / (ms / 1e3)
@@ -144,6 +161,9 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                        "p99": round(float(np.percentile(lat_ms, 99)), 3), "mode": "plain per-frame pipeline"},
         "sweep_sgm_only_value": round(ks_value, 1),
+        "host_io": ({"ms_per_frame": round(host_ms, 3), "value": round(hyp / 1e6 / (host_ms / 1e3), 1),
+                     "unit": "Mpx·hyp/s", "note": "host buffers in and out (PCIe included); not the headline value"}
+                    if host_ms else None),
         "stage_ms_per_frame": {k: round(v[0] / args.steps, 4) for k, v in times.items() if v[1]},
         "sweep_label_inflation": round(work["sweep_evaluated"] / hyp, 4) if hyp else None,
         "roofline": roof,

@@ -9,8 +9,10 @@
 // Precision: geometry in double.  Where a floating-point value decides an
 // integer result (the census bits decided by warped intensities) the value
 // is computed in the same precision the GPU kernel uses: sample coordinates
-// in double, bilinear interpolation in float with an explicit operation
-// order.  Built with -ffp-contract=off so that no multiply-add is fused.
+// in double, bilinear interpolation in float, every operation spelled out
+// (explicit fused multiply-adds through std::fma where the definition has
+// them).  Built with -ffp-contract=off so that the compiler fuses nothing
+// else.
 //
 // Conventions (readings of passages the paper leaves open):
 //  * pixel (x, y) has its centre at (x+0.5, y+0.5) in the coordinates K maps

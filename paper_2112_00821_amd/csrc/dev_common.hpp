@@ -48,25 +48,25 @@ __device__ __forceinline__ float warp_sample(const uint8_t *__restrict__ src, in
     return __builtin_fmaf(ay, bot - top, top);
 }
 
-// Minimum over the 64 lanes of a wavefront: DPP within each row of 16, then
-// the four row results through readlane.  Every lane must be active.
+// Minimum over the 64 lanes of a wavefront: DPP within each row of 16
+// (quad_perm, row_half_mirror, row_mirror), then row_bcast:15 and
+// row_bcast:31 carry the row minima up to lane 63, which is read back.
+// Every lane must be active.
+// Lanes of rows outside ROW_MASK see the identity (all ones), so the
+// minimum leaves them unchanged and the move folds into the min as DPP.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_min_step(uint32_t v) {
+    const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, CTRL, ROW_MASK, 0xF, false);
+    return v < t ? v : t;
+}
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-    uint32_t t;
-    t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
-    v = v < t ? v : t;
-    t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
-    v = v < t ? v : t;
-    t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-    v = v < t ? v : t;
-    t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
-    v = v < t ? v : t;
-    uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
-    uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
-    uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
-    uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
-    a = a < b ? a : b;
-    c = c < d ? c : d;
-    return a < c ? a : c;
+    v = dpp_min_step<0xB1, 0xF>(v);    // quad_perm 1,0,3,2
+    v = dpp_min_step<0x4E, 0xF>(v);    // quad_perm 2,3,0,1
+    v = dpp_min_step<0x141, 0xF>(v);   // row_half_mirror
+    v = dpp_min_step<0x140, 0xF>(v);   // row_mirror: every lane holds its row's minimum
+    v = dpp_min_step<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_min_step<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ __forceinline__ void ray_of(const double *Ki, double u, double v, double r[3]) {

@@ -17,6 +17,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace fmvs {
 
@@ -68,9 +69,10 @@ int sgm_paths(int dir, int w, int h) {
 
 // Path costs of one direction, written to that direction's buffer.  Loads
 // run ahead of the recursion: a ring of PF steps holds each lane's cost
-// bytes, and the per-step uniform values (reference intensity, window
-// offsets, surface-normal offsets) of 64 steps are fetched by one vector
-// load per quantity (lane j holds step t0 + j) and read back with readlane.
+// bytes, and the per-step uniform values (the P2 penalty of the step's
+// intensity change, window offsets, surface-normal offsets) of 64 steps are
+// fetched by one vector load per quantity (lane j holds step t0 + j) and
+// read back with readlane.
 // NF bounds the plane families (1, or up to the maximum), which sizes the
 // per-family registers.
 template <int K, int NF, bool WIN, bool SN, bool PG>
@@ -125,9 +127,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
 
     // per-step uniform values, 64 steps per chunk
     auto load_chunk = [&](int t0, int &ref_v, int (&off_v)[NF], int (&di_v)[NF]) {
-        int t = t0 + lane;
-        long p = p0 + (long)(t < len ? t : len - 1) * pstride;
-        ref_v = a.ref[p];
+        // ref_v: the penalty P2 of step t = t0 + lane, from the intensity
+        // step between its pixel and the previous one on the path
+        const int t = t0 + lane < len ? t0 + lane : len - 1;
+        const long p = p0 + (long)t * pstride;
+        const long pp = p0 + (long)(t > 0 ? t - 1 : 0) * pstride;
+        const int di = (int)a.ref[p] - (int)a.ref[pp];
+        ref_v = a.lut[di < 0 ? -di : di];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             off_v[f] = (WIN && f < F) ? a.offs[(size_t)f * N + p] : 0;
@@ -150,7 +156,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
 
     uint32_t L[K];
     uint32_t Mq = 0;
-    int Iq = 0;
     int oq[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) oq[f] = 0;
@@ -181,7 +186,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) ring[u][k] = lv[k] ? S[(size_t)pn * D + k * 64 + lane] : 0u;
             }
-            const int Ip = __builtin_amdgcn_readlane(c_ref, lb + u);
+            const uint32_t P2 = (uint32_t)__builtin_amdgcn_readlane(c_ref, lb + u);
             int op[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) op[f] = WIN ? __builtin_amdgcn_readlane(c_off[f], lb + u) : 0;
@@ -191,8 +196,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) L[k] = sv[k];
             } else {
-                int dI = Ip - Iq;
-                const uint32_t P2 = (uint32_t)a.lut[dI < 0 ? -dI : dI];
                 const uint32_t P1 = (uint32_t)a.p1;
                 int sh[NF];
 #pragma unroll
@@ -276,9 +279,226 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm(const SgmArgs a) {
             } else {
                 Mq = wave_min_u32(m);
             }
-            Iq = Ip;
 #pragma unroll
             for (int f = 0; f < NF; ++f) oq[f] = op[f];
+        }
+    }
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// Path costs of one direction with two labels per lane as packed 16-bit
+// values (labels 2i, 2i+1 of pair i = 64k + lane in register k).  Same
+// recursion and results as k_sgm; every family window must hold an even
+// number of labels so no pair straddles two families.  The predecessor
+// buffer holds 16-bit costs with six +inf guards around each family
+// segment; a pair's three taps (j-1, j), (j, j+1), (j+1, j+2) come from
+// two or three aligned 32-bit LDS reads and byte permutes, whichever parity
+// the shifted index j has.  P1 is added with unsigned saturation so the
+// guards stay +inf; every finite sum stays below 2^16 by the configuration
+// bound.  Global traffic goes through buffer resources rebuilt per step on
+// the scalar unit (row base = pixel of the step): the lane offset is the
+// only vector operand, and lanes past the label count read 0 and drop their
+// stores by the resource's range check.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
+}
+
+template <int KP, int NF, bool WIN, bool SN>
+__global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
+    constexpr int PF = 16;
+    constexpr int G2 = 6;
+    constexpr int LW = (kMaxLabels + 2 * G2 * kMaxFam) / 2 + 1;   // 32-bit words per buffer, last one a sink
+    __shared__ uint32_t lbuf[WAVES][2][LW];
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int path = blockIdx.x * WAVES + wid;
+    if (path >= a.path_begin[a.n_dirs]) return;
+    int slot = 0;
+    while (path >= a.path_begin[slot + 1]) ++slot;
+    const int dir = a.dirs[slot];
+    const PathGeom pg = path_geom(dir, path - a.path_begin[slot], a.w, a.h);
+    const size_t N = (size_t)a.w * a.h;
+    const int D = a.D;
+    const int F = NF == 1 ? 1 : a.n_fam;
+    const long pstride = (long)pg.dy * a.w + pg.dx;
+    const long p0 = (long)pg.sy * a.w + pg.sx;
+    const int len = pg.len;
+    const bool all_valid = D == 128 * KP;
+
+    int fam[KP], li[KP], jmax[KP], seg[KP], widx[KP];
+    uint32_t lo8[KP];   // byte offset of the pair inside a pixel's cost row
+    bool lv[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int i = 2 * (k * 64 + lane);   // first label of the pair
+        lo8[k] = (uint32_t)i;
+        lv[k] = i < D;
+        int f = 0;
+        while (f + 1 < F && i >= a.foff[f + 1]) ++f;
+        fam[k] = f;
+        li[k] = i - a.foff[f];
+        jmax[k] = a.W[f] + 2;
+        int sb = G2;
+        for (int ff = 0; ff < f; ++ff) sb += a.W[ff] + 2 * G2;
+        seg[k] = sb;
+        widx[k] = lv[k] ? (sb + li[k]) >> 1 : LW - 1;
+    }
+    uint32_t *buf0 = lbuf[wid][0];
+    uint32_t *buf1 = lbuf[wid][1];
+    for (int i = lane; i < LW; i += 64) {
+        buf0[i] = 0xFFFFFFFFu;
+        buf1[i] = 0xFFFFFFFFu;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    const uint8_t *__restrict__ S = a.S;
+    uint16_t *__restrict__ out = a.out[slot];
+
+    auto load_chunk = [&](int t0, int &ref_v, int (&off_v)[NF], int (&di_v)[NF]) {
+        // ref_v: the penalty P2 of step t = t0 + lane, from the intensity
+        // step between its pixel and the previous one on the path
+        const int t = t0 + lane < len ? t0 + lane : len - 1;
+        const long p = p0 + (long)t * pstride;
+        const long pp = p0 + (long)(t > 0 ? t - 1 : 0) * pstride;
+        const int di = (int)a.ref[p] - (int)a.ref[pp];
+        ref_v = a.lut[di < 0 ? -di : di];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            off_v[f] = (WIN && f < F) ? a.offs[(size_t)f * N + p] : 0;
+            di_v[f] = (SN && f < F) ? (int)a.dI[((size_t)dir * N + p) * F + f] : 0;
+        }
+    };
+    int c_ref, n_ref;
+    int c_off[NF], n_off[NF], c_di[NF], n_di[NF];
+    load_chunk(0, c_ref, c_off, c_di);
+    if (len > 64) load_chunk(64, n_ref, n_off, n_di);
+
+    // ring of cost byte pairs, PF steps ahead (steps past the path's end
+    // re-read its last pixel)
+    uint32_t ring[PF][KP];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        const long p = p0 + (long)(u < len ? u : len - 1) * pstride;
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(S + (size_t)p * D, D);
+#pragma unroll
+        for (int k = 0; k < KP; ++k) ring[u][k] = __builtin_amdgcn_raw_buffer_load_b16(rs, lo8[k], 0, 0);
+    }
+
+    u16x2 L[KP];
+    uint32_t Mq = 0;
+    int oq[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) oq[f] = 0;
+
+    // one step of the recursion at path position t (ring slot u)
+    auto step = [&](const int t, const int u, const int lb, const bool first) __attribute__((always_inline)) {
+        // PF divides 64, so the 64-step chunk of t is the current one
+        const long p = p0 + (long)t * pstride;
+        u16x2 sv[KP];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) sv[k] = as_u16x2(__builtin_amdgcn_perm(0u, ring[u][k], 0x0c010c00u));
+        {
+            const int tn = t + PF < len ? t + PF : len - 1;
+            const __amdgpu_buffer_rsrc_t rs = row_rsrc(S + (size_t)(p0 + (long)tn * pstride) * D, D);
+#pragma unroll
+            for (int k = 0; k < KP; ++k) ring[u][k] = __builtin_amdgcn_raw_buffer_load_b16(rs, lo8[k], 0, 0);
+        }
+        const uint32_t P2 = (uint32_t)__builtin_amdgcn_readlane(c_ref, lb + u);
+        int op[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) op[f] = WIN ? __builtin_amdgcn_readlane(c_off[f], lb + u) : 0;
+        uint32_t *cur = (u & 1) ? buf1 : buf0;
+        const uint32_t *prev = (u & 1) ? buf0 : buf1;
+        if (first) {
+#pragma unroll
+            for (int k = 0; k < KP; ++k) L[k] = sv[k];
+        } else {
+            const uint32_t P1 = (uint32_t)a.p1;
+            const u16x2 p1v = as_u16x2(P1 | (P1 << 16));
+            const u16x2 mqv = as_u16x2(Mq | (Mq << 16));
+            const uint32_t fl = Mq + P2;
+            const u16x2 flv = as_u16x2(fl | (fl << 16));
+            int sh[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                int v = WIN ? op[f] - oq[f] : 0;
+                if (SN) v += __builtin_amdgcn_readlane(c_di[f], lb + u);
+                sh[f] = v;
+            }
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                int sft = sh[0];
+#pragma unroll
+                for (int f = 1; f < NF; ++f)
+                    if (fam[k] == f) sft = sh[f];
+                const int jm = NF == 1 ? a.W[0] + 2 : jmax[k];
+                const int sg = NF == 1 ? G2 : seg[k];
+                const int j = min(max(li[k] + sft, -4), jm);
+                const int base = sg + j;
+                // one family: every lane shares the shift's parity (the
+                // clamp bounds are even and read only guards either way)
+                const bool odd = NF == 1 ? (sft & 1) : (base & 1);
+                uint32_t wm, w0, wp;
+                if (odd) {
+                    const int e = (base - 1) >> 1;
+                    const uint32_t Y = prev[e], Z = prev[e + 1];
+                    wm = Y;
+                    w0 = __builtin_amdgcn_alignbit(Z, Y, 16);
+                    wp = Z;
+                } else {
+                    const int e = base >> 1;
+                    const uint32_t X = prev[e - 1], Y = prev[e], Z = prev[e + 1];
+                    wm = __builtin_amdgcn_alignbit(Y, X, 16);
+                    w0 = Y;
+                    wp = __builtin_amdgcn_alignbit(Z, Y, 16);
+                }
+                const u16x2 cm = as_u16x2(wm), c0 = as_u16x2(w0), cp = as_u16x2(wp);
+                const u16x2 c1 = __builtin_elementwise_add_sat(__builtin_elementwise_min(cm, cp), p1v);
+                u16x2 best = __builtin_elementwise_min(c0, c1);
+                best = __builtin_elementwise_min(best, flv);
+                L[k] = sv[k] + (best - mqv);
+            }
+        }
+        u16x2 m2 = as_u16x2(0xFFFFFFFFu);
+        const __amdgpu_buffer_rsrc_t ro = row_rsrc(out + (size_t)p * D, 2 * D);
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            cur[widx[k]] = as_u32(L[k]);
+            __builtin_amdgcn_raw_buffer_store_b32(as_u32(L[k]), ro, 2 * lo8[k], 0, 0);
+            m2 = __builtin_elementwise_min(m2, (all_valid || lv[k]) ? L[k] : as_u16x2(0xFFFFFFFFu));
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t mw = as_u32(m2);
+        const uint32_t lo = mw & 0xFFFFu, hi = mw >> 16;
+        Mq = wave_min_u32(lo < hi ? lo : hi);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) oq[f] = op[f];
+    };
+
+    for (int t0 = 0; t0 < len; t0 += PF) {
+        if (t0 > 0 && (t0 & 63) == 0) {
+            c_ref = n_ref;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                c_off[f] = n_off[f];
+                c_di[f] = n_di[f];
+            }
+            if (t0 + 64 < len) load_chunk(t0 + 64, n_ref, n_off, n_di);
+        }
+        const int lb = t0 & 63;   // PF divides 64
+        if (t0 > 0 && t0 + PF <= len) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) step(t0 + u, u, lb, false);
+        } else {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                if (t0 + u >= len) break;
+                step(t0 + u, u, lb, t0 + u == 0);
+            }
         }
     }
 }
@@ -459,6 +679,35 @@ static void launch_k(const SgmArgs &a, bool win, bool sn, dim3 grid, hipStream_t
 #undef FMVS_SGM
 }
 
+template <int KP>
+static void launch_pk(const SgmArgs &a, bool win, bool sn, dim3 grid, hipStream_t s) {
+#define FMVS_SGMPK(W_, S_)                                                                    \
+    if (win == W_ && sn == S_) {                                                              \
+        if (a.n_fam == 1)                                                                     \
+            hipLaunchKernelGGL((k_sgm_pk<KP, 1, W_, S_>), grid, dim3(64 * WAVES), 0, s, a);   \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_sgm_pk<KP, kMaxFam, W_, S_>), grid, dim3(64 * WAVES), 0, s, a); \
+        return;                                                                               \
+    }
+    FMVS_SGMPK(false, false)
+    FMVS_SGMPK(true, false)
+    FMVS_SGMPK(false, true)
+    FMVS_SGMPK(true, true)
+#undef FMVS_SGMPK
+}
+
+// Packed two-label kernel when every family window is even and the
+// path-gradient variant is off; the one-label kernel otherwise.
+static bool use_packed(const SgmArgs &a) {
+    if (a.final_mode || a.pg || (a.D & 1)) return false;
+    for (int f = 0; f < a.n_fam; ++f)
+        if (a.W[f] & 1) return false;
+    // FASSMVS_SGM_UNPACKED=1 selects the one-label kernel (same results);
+    // read per launch so a process can run both
+    const char *e = std::getenv("FASSMVS_SGM_UNPACKED");
+    return !(e && std::atoi(e) != 0);
+}
+
 hipError_t launch_sgm(const SgmArgs &a0, hipStream_t s) {
     SgmArgs a = a0;
     a.path_begin[0] = 0;
@@ -469,6 +718,16 @@ hipError_t launch_sgm(const SgmArgs &a0, hipStream_t s) {
     dim3 grid((unsigned)((paths + WAVES - 1) / WAVES));
     bool win = a.offs != nullptr, sn = a.dI != nullptr;
     if (a.pg && (sn || a.sumG > kMaxPgPlanes || !a.delta)) return hipErrorInvalidValue;
+    if (use_packed(a)) {
+        switch ((a.D + 127) / 128) {
+            case 1: launch_pk<1>(a, win, sn, grid, s); break;
+            case 2: launch_pk<2>(a, win, sn, grid, s); break;
+            case 3: launch_pk<3>(a, win, sn, grid, s); break;
+            case 4: launch_pk<4>(a, win, sn, grid, s); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     int K = (a.D + 63) / 64;
     switch (K) {
         case 1: launch_k<1>(a, win, sn, grid, s); break;

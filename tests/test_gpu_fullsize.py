@@ -107,12 +107,12 @@ def test_coarsest_level(orc, run):
             assert np.mean(h.level_map(top - 1, 7) == seed["dI"]) >= 0.9999
         return
     # sampled costs of the coarsest level over every family's full list (the
-    # pipeline keeps only level 0's volume, so the cost stage entry point
-    # recomputes it from the pipeline's own pyramid and census)
+    # pipeline keeps only level 0's census and volume, so the stage entry
+    # points recompute them from the pipeline's own pyramid)
     Ki, plan, H = _level(orc, wl, top)
     img, views = _views_at(orc, wl, top)
     assert np.array_equal(h.level_map(top, 30), img)
-    ctd = h.upload(h.level_map(top, 20))
+    ctd = h.stage_census(h.upload(h.level_map(top, 30)), 9, 7)
     vd = [h.upload(h.level_map(top, 31 + k)) for k in range(len(views))]
     S = h.stage_cost(ctd, vd, wl["side"], 9, 7, plan["G"], plan["W"], H).numpy()
     hh, ww = S.shape[:2]
@@ -120,7 +120,7 @@ def test_coarsest_level(orc, run):
     xy = np.stack([rng.integers(0, ww, 300), rng.integers(0, hh, 300)], -1)
     xy = np.concatenate([xy, [[0, 0], [ww - 1, hh - 1], [ww - 1, 0], [0, hh - 1]]]).astype(np.int32)
     ct = orc.census(img, 9, 7)
-    assert np.array_equal(h.level_map(top, 20), ct)
+    assert np.array_equal(ctd.numpy(), ct)
     exp = orc.cost_pixels(ct, views, wl["side"], 9, 7, plan["G"], plan["W"], H, xy)
     got = S[xy[:, 1], xy[:, 0]]
     assert np.mean(got == exp) >= 0.9999

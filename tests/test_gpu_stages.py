@@ -248,3 +248,39 @@ def test_sgm_path_gradient_bit_exact(orc, hd, name, level):
     assert np.array_equal(r["Lr"].numpy(), Lr)
     assert np.array_equal(r["Sbar"].numpy(), Sbar)
     assert np.array_equal(r["wta"].numpy(), np.argmin(Sbar, axis=-1))
+
+
+@pytest.mark.parametrize("kernel", ["packed", "one-label"])
+@pytest.mark.parametrize("shape,W,G,paths", [
+    ((37, 53), [24, 16, 32], [40, 16, 64], 8),      # even windows, 72 labels
+    ((37, 53), [23, 16, 9], [40, 16, 12], 8),       # odd windows (one-label kernel either way)
+    ((21, 30), [200, 130], [260, 130], 8),          # 330 labels: three packed registers, ragged
+    ((19, 26), [128], [256], 4),                    # exactly 128 labels, four paths
+    ((1, 41), [16, 8], [30, 8], 8),                 # one-row image
+    ((33, 1), [16], [16], 8),                       # one-column image
+])
+def test_sgm_random_volumes(orc, hd, monkeypatch, kernel, shape, W, G, paths):
+    """Random costs, window offsets over the whole plane list and
+    surface-normal offsets over [-7, 7] (shifts reach far into and past the
+    guards): path costs, aggregate and winners bit-exact with the oracle,
+    for the packed two-label kernel and the one-label kernel."""
+    if kernel == "one-label":
+        monkeypatch.setenv("FASSMVS_SGM_UNPACKED", "1")
+    else:
+        monkeypatch.delenv("FASSMVS_SGM_UNPACKED", raising=False)
+    h, w = shape
+    rng = np.random.default_rng(sum(W) * 131 + h * 7 + w)
+    F = len(W)
+    D = int(sum(W))
+    S = rng.integers(0, 64, (h, w, D), dtype=np.uint8)
+    offs = np.stack([rng.integers(0, g - wf + 1, (h, w)) for g, wf in zip(G, W)]).astype(np.int32)
+    dI = rng.integers(-7, 8, (8, h, w, F)).astype(np.int8)
+    ref = rng.integers(0, 256, (h, w), dtype=np.uint8)
+    p1 = 8
+    lut = orc.p2_lut(p1, 1, 64, 8.0, 10.0)
+    Sbar, Lr = orc.sgm(S, W, p1, lut, ref, paths, offs=offs, dI=dI, want_lr=True)
+    r = hd.stage_sgm(hd.upload(S), W, p1, lut, hd.upload(ref), paths, offs=hd.upload(offs), dI=hd.upload(dI),
+                     want_lr=True, want_sbar=True)
+    assert np.array_equal(r["Lr"].numpy(), Lr)
+    assert np.array_equal(r["Sbar"].numpy(), Sbar)
+    assert np.array_equal(r["wta"].numpy(), np.argmin(Sbar, axis=-1))
