@@ -69,6 +69,9 @@ def _declare(L):
         "or_cost_volume": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, vp, vp, vp]),
         "or_cost_sample": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, i, i, i, i]),
         "or_cost_pixels": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, vp, vp, i, vp, vp]),
+        "or_ncc_cost_volume": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, vp, vp, vp]),
+        "or_ncc_cost_pixels": (i, [i, i, vp, i, vp, vp, i, i, i, vp, vp, vp, vp, i, vp, vp]),
+        "or_ncc_window": (i, [vp, vp, i, i]),
         "or_sgm": (i, [i, i, i, vp, vp, vp, vp, i, vp, vp, i, vp, vp]),
         "or_sgm_pg": (i, [i, i, i, vp, vp, vp, vp, i, vp, vp, i, vp, vp, i, vp, vp, vp, vp, vp]),
         "or_wta_refine": (None, [i, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
@@ -183,6 +186,51 @@ def cost_volume(ct_ref, views, side, cw, ch, G, W, H, offs=None):
     if r != 0:
         raise ValueError("cost volume: bad arguments or 8-bit overflow (%d)" % r)
     return S
+
+
+def ncc_cost_volume(ref_img, views, side, cw, ch, G, W, H, offs=None):
+    """NCC cost volume S[h][w][sum W] uint8 (negated, truncated, scaled NCC;
+    mean over each subset); H: [n_views][sum G][3][3]."""
+    ref_img = _c(ref_img, np.uint8)
+    h, w = ref_img.shape
+    G = np.asarray(G, np.int32)
+    W = np.asarray(W, np.int32)
+    arrs, ptrs = _view_ptrs(views)
+    side = _c(side, np.int8)
+    H = _c(H, np.float64)
+    S = np.zeros((h, w, int(W.sum())), np.uint8)
+    offs_c = _c(offs, np.int32) if offs is not None else None
+    r = lib().or_ncc_cost_volume(w, h, _p(ref_img), len(arrs), C.cast(ptrs, C.c_void_p), _p(side), cw, ch,
+                                 len(G), _p(G), _p(W), _p(H), _p(offs_c), _p(S))
+    if r != 0:
+        raise ValueError("ncc cost volume: bad arguments (%d)" % r)
+    return S
+
+
+def ncc_cost_pixels(ref_img, views, side, cw, ch, G, W, H, xy, offs=None):
+    """NCC cost vectors [n][sum W] of the pixels xy ([n][2] as x, y)."""
+    ref_img = _c(ref_img, np.uint8)
+    h, w = ref_img.shape
+    G = np.asarray(G, np.int32)
+    W = np.asarray(W, np.int32)
+    xy = _c(xy, np.int32)
+    arrs, ptrs = _view_ptrs(views)
+    out = np.zeros((len(xy), int(W.sum())), np.uint8)
+    r = lib().or_ncc_cost_pixels(w, h, _p(ref_img), len(arrs), C.cast(ptrs, C.c_void_p), _p(_c(side, np.int8)),
+                                 cw, ch, len(G), _p(G), _p(W), _p(_c(H, np.float64)),
+                                 _p(_c(offs, np.int32) if offs is not None else None), len(xy), _p(xy), _p(out))
+    if r != 0:
+        raise ValueError("ncc_cost_pixels failed (%d)" % r)
+    return out
+
+
+def ncc_window(a, b):
+    """NCC cost of one pair of windows: a uint8 [ch][cw] (reference), b
+    float32 [ch][cw] (warped view)."""
+    a = _c(a, np.uint8)
+    b = _c(b, np.float32)
+    ch, cw = a.shape
+    return int(lib().or_ncc_window(_p(a), _p(b), cw, ch))
 
 
 def cost_sample(ct_ref, views, side, cw, ch, G, H, f, g, x, y):
@@ -346,7 +394,10 @@ def run_frame(wl, keep=False, levels_only=None):
     ref = wl["ref"]
     views = wl["views"]
     side = np.asarray(wl["side"], np.int8)
-    m = subset_multiplier(wl["side"])
+    ncc = p.get("cost", "census") == "ncc"
+    # the NCC cost is a subset mean on the 0..255 scale of one view, the
+    # census cost a sum scaled by m: P1 and fixed P2 scale alike
+    m = 1 if ncc else subset_multiplier(wl["side"])
     p1 = m * p["p1"]
     lut = p2_lut(p1, p["p2_mode"], m * p["p2_fixed"], p["p2_alpha"], p["p2_beta"])
     cw, chh = p["census_w"], p["census_h"]
@@ -373,10 +424,13 @@ def run_frame(wl, keep=False, levels_only=None):
                 for j, dv in enumerate(dl):
                     H[k, g0 + j] = homography(Kl, Ki, R, t, plan["fam_n"][f], dv)
                 g0 += len(dl)
-        ct = census(img, cw, chh)
+        ct = None if ncc else census(img, cw, chh)
         top = l == n - 1
         o = None if top or p["window_labels"] <= 0 else offs
-        S = cost_volume(ct, [pv[l] for pv in pyr_views], side, cw, chh, plan["G"], plan["W"], H, o)
+        if ncc:
+            S = ncc_cost_volume(img, [pv[l] for pv in pyr_views], side, cw, chh, plan["G"], plan["W"], H, o)
+        else:
+            S = cost_volume(ct, [pv[l] for pv in pyr_views], side, cw, chh, plan["G"], plan["W"], H, o)
         use_dI = (not top) and p["sgm_variant"] == 1 and dI is not None
         fam_delta = np.concatenate(plan["deltas"])
         pg = None

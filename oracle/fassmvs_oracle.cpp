@@ -111,6 +111,60 @@ inline int combine_lr(long sL, long sR, int nL, int nR) {
     return (int)best;
 }
 
+// S for the NCC cost: min over the non-empty subsets X of floor(s^X / |X|),
+// the mean cost of a subset, which stays on the 0..255 scale of one view
+// (the paper normalises the NCC cost's maximum to 255).
+inline int combine_mean(long sL, long sR, int nL, int nR) {
+    long best = -1;
+    if (nL > 0) best = sL / nL;
+    if (nR > 0) {
+        long v = sR / nR;
+        best = best < 0 ? v : std::min(best, v);
+    }
+    return (int)best;
+}
+
+// Negated, truncated and scaled normalised cross-correlation of two cw x ch
+// windows a (reference, integer intensities) and b (warped view), both
+// row-major (matching cost of Alg. 1 with the NCC similarity).  Sums run
+// along each row left to right, then over the rows top to bottom, in
+// double; products are fused multiply-adds:
+//   n = cw*ch, vA = n*sAA - sA*sA, vB = n*sBB - sB*sB, cov = n*sAB - sA*sB,
+//   rho = cov / sqrt(vA * vB)  (0 when vA or vB is not positive),
+//   clamped to [-1, 1];  C = floor(255 * min(1, 1 - rho) + 0.5).
+// A flat window therefore costs 255, and anti-correlation is truncated at
+// the same maximum.
+inline int ncc_cost(const uint8_t* a, const float* b, int cw, int ch) {
+    double sA = 0, sAA = 0, sB = 0, sBB = 0, sAB = 0;
+    for (int y = 0; y < ch; ++y) {
+        double rA = 0, rAA = 0, rB = 0, rBB = 0, rAB = 0;
+        for (int x = 0; x < cw; ++x) {
+            const double va = a[y * cw + x];
+            const double vb = b[y * cw + x];
+            if (x == 0) {
+                rA = va; rAA = va * va; rB = vb; rBB = vb * vb; rAB = va * vb;
+            } else {
+                rA = rA + va; rAA = std::fma(va, va, rAA);
+                rB = rB + vb; rBB = std::fma(vb, vb, rBB); rAB = std::fma(va, vb, rAB);
+            }
+        }
+        if (y == 0) {
+            sA = rA; sAA = rAA; sB = rB; sBB = rBB; sAB = rAB;
+        } else {
+            sA = sA + rA; sAA = sAA + rAA; sB = sB + rB; sBB = sBB + rBB; sAB = sAB + rAB;
+        }
+    }
+    const double n = (double)(cw * ch);
+    const double vA = n * sAA - sA * sA;
+    const double vB = n * sBB - sB * sB;
+    const double cov = n * sAB - sA * sB;
+    double rho = 0.0;
+    if (vA > 0.0 && vB > 0.0) rho = cov / std::sqrt(vA * vB);
+    rho = std::min(1.0, std::max(-1.0, rho));
+    const double c = std::min(1.0, 1.0 - rho);
+    return (int)std::floor(255.0 * c + 0.5);
+}
+
 inline void ray_of(const double* Ki, double u, double v, double r[3]) {
     r[0] = Ki[0] * u + Ki[1] * v + Ki[2];
     r[1] = Ki[3] * u + Ki[4] * v + Ki[5];
@@ -382,6 +436,108 @@ int or_cost_pixels(int w, int h, const uint64_t* ct_ref, int n_views, const uint
     }
     return 0;
 }
+
+// ---------------------------------------------------------------------------
+// NCC cost volume (Alg. 1 with the negated, truncated and scaled NCC as the
+// matching cost, Sec. on the similarity measures): for every pixel, label and
+// view, the cw x ch window of the reference (replicate border) against the
+// same window of the warped view; S = combine_mean of the left and right
+// sums.  Arguments as or_cost_volume with the reference image in place of its
+// census.
+// ---------------------------------------------------------------------------
+int or_ncc_cost_volume(int w, int h, const uint8_t* ref, int n_views, const uint8_t* const* views,
+                       const int8_t* side, int cw, int ch, int n_fam, const int* G, const int* W,
+                       const double* H, const int32_t* offs, uint8_t* S) {
+    int D = 0, sumG = 0;
+    std::vector<int> foff(n_fam), goff(n_fam);
+    for (int f = 0; f < n_fam; ++f) {
+        foff[f] = D; goff[f] = sumG;
+        D += W[f]; sumG += G[f];
+        if (!offs && W[f] != G[f]) return -1;
+    }
+    int nL = 0, nR = 0;
+    for (int k = 0; k < n_views; ++k) (side[k] < 0 ? nL : nR)++;
+    const int rx = cw / 2, ry = ch / 2;
+    size_t N = (size_t)w * h;
+    std::vector<int32_t> sL(N * D, 0), sR(N * D, 0);
+    std::vector<float> warped(N), wb((size_t)cw * ch);
+    std::vector<uint8_t> wa((size_t)cw * ch);
+    for (int k = 0; k < n_views; ++k)
+        for (int f = 0; f < n_fam; ++f)
+            for (int g = 0; g < G[f]; ++g) {
+                bool needed = false;
+                for (size_t p = 0; p < N && !needed; ++p) {
+                    int o = offs ? offs[(size_t)f * N + p] : 0;
+                    needed = g >= o && g < o + W[f];
+                }
+                if (!needed) continue;
+                const double* Hk = H + ((size_t)k * sumG + goff[f] + g) * 9;
+                or_warp(views[k], w, h, Hk, w, h, warped.data());
+                for (int y = 0; y < h; ++y)
+                    for (int x = 0; x < w; ++x) {
+                        size_t p = (size_t)y * w + x;
+                        int o = offs ? offs[(size_t)f * N + p] : 0;
+                        if (g < o || g >= o + W[f]) continue;
+                        for (int dy = -ry; dy <= ry; ++dy)
+                            for (int dx = -rx; dx <= rx; ++dx) {
+                                int xx = clampi(x + dx, 0, w - 1), yy = clampi(y + dy, 0, h - 1);
+                                wa[(size_t)(dy + ry) * cw + dx + rx] = ref[(size_t)yy * w + xx];
+                                wb[(size_t)(dy + ry) * cw + dx + rx] = warped[(size_t)yy * w + xx];
+                            }
+                        int c = ncc_cost(wa.data(), wb.data(), cw, ch);
+                        size_t idx = p * D + foff[f] + (g - o);
+                        if (side[k] < 0) sL[idx] += c; else sR[idx] += c;
+                    }
+            }
+    for (size_t i = 0; i < N * (size_t)D; ++i) S[i] = (uint8_t)combine_mean(sL[i], sR[i], nL, nR);
+    return 0;
+}
+
+// The NCC cost vectors of a list of pixels, each entry computed on its own
+// from warped samples of the window (same definition as or_ncc_cost_volume).
+int or_ncc_cost_pixels(int w, int h, const uint8_t* ref, int n_views, const uint8_t* const* views,
+                       const int8_t* side, int cw, int ch, int n_fam, const int* G, const int* W,
+                       const double* H, const int32_t* offs, int n_pix, const int32_t* xy, uint8_t* out) {
+    int D = 0, sumG = 0;
+    std::vector<int> goff(n_fam);
+    for (int f = 0; f < n_fam; ++f) { goff[f] = sumG; D += W[f]; sumG += G[f]; }
+    int nL = 0, nR = 0;
+    for (int k = 0; k < n_views; ++k) (side[k] < 0 ? nL : nR)++;
+    const int rx = cw / 2, ry = ch / 2;
+    size_t N = (size_t)w * h;
+    std::vector<float> wb((size_t)cw * ch);
+    std::vector<uint8_t> wa((size_t)cw * ch);
+    for (int i = 0; i < n_pix; ++i) {
+        int x = xy[2 * i], y = xy[2 * i + 1];
+        if (x < 0 || x >= w || y < 0 || y >= h) return -1;
+        for (int dy = -ry; dy <= ry; ++dy)
+            for (int dx = -rx; dx <= rx; ++dx)
+                wa[(size_t)(dy + ry) * cw + dx + rx] =
+                    ref[(size_t)clampi(y + dy, 0, h - 1) * w + clampi(x + dx, 0, w - 1)];
+        int l = 0;
+        for (int f = 0; f < n_fam; ++f) {
+            int o = offs ? offs[(size_t)f * N + (size_t)y * w + x] : 0;
+            for (int j = 0; j < W[f]; ++j, ++l) {
+                long sl = 0, sr = 0;
+                for (int k = 0; k < n_views; ++k) {
+                    const double* Hk = H + ((size_t)k * sumG + goff[f] + o + j) * 9;
+                    for (int dy = -ry; dy <= ry; ++dy)
+                        for (int dx = -rx; dx <= rx; ++dx) {
+                            int xx = clampi(x + dx, 0, w - 1), yy = clampi(y + dy, 0, h - 1);
+                            wb[(size_t)(dy + ry) * cw + dx + rx] = warp_sample(views[k], w, h, Hk, xx + 0.5, yy + 0.5);
+                        }
+                    int c = ncc_cost(wa.data(), wb.data(), cw, ch);
+                    if (side[k] < 0) sl += c; else sr += c;
+                }
+                out[(size_t)i * D + l] = (uint8_t)combine_mean(sl, sr, nL, nR);
+            }
+        }
+    }
+    return 0;
+}
+
+// NCC cost of one pair of windows (the definition above), for the pins.
+int or_ncc_window(const uint8_t* a, const float* b, int cw, int ch) { return ncc_cost(a, b, cw, ch); }
 
 // ---------------------------------------------------------------------------
 // Semi-global aggregation (Eq. sgm-path, sgm-smooth, sgm-aggr for SGM^Pi in
