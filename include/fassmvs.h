@@ -60,11 +60,13 @@ typedef int32_t fassmvs_status;
 
 typedef struct {
     int32_t n_levels;          /* pyramid height n, 1..5 (pipeline overview) */
-    int32_t census_w;          /* census window width, 5 or 9 (similarity-measure experiment) */
-    int32_t census_h;          /* census window height, 5 or 7 */
+    int32_t census_w;          /* matching window width: census 3, 5, 7, 9; NCC 3, 5, 7, 9
+                                  (similarity-measure experiment) */
+    int32_t census_h;          /* matching window height: census 3, 5, 7 (with width 3, 5, 7, 9);
+                                  NCC equal to the width */
     int32_t n_paths;           /* 8, or 4 (diagonals dropped) */
     int32_t sgm_variant;       /* 0: SGM^Pi; 1: SGM^Pi-sn below the coarsest level; 2: SGM^Pi-pg */
-    int32_t p1;                /* P1 per matching image; scaled by m = max(|L|,|R|) */
+    int32_t p1;                /* P1 per matching image; census: scaled by m = max(|L|,|R|) */
     int32_t p2_mode;           /* 0: fixed P2; 1: adaptive P2 (Eq. p2-grad) */
     int32_t p2_fixed;          /* P2 per matching image in fixed mode (>= p1) */
     double p2_alpha;           /* alpha of Eq. p2-grad (paper: 8) */
@@ -80,6 +82,11 @@ typedef struct {
     int32_t profile;           /* 1: time every stage with HIP events */
     int32_t keep_levels;       /* 1: keep per-level maps of the last frame (fassmvs_level_map) */
     int32_t sgm_debug;         /* 1: write every path's costs and the full aggregate (tests) */
+    int32_t cost;              /* matching cost of Alg. 1 (Sec. on the similarity measures):
+                                  0 census-Hamming, S = min over non-empty subsets X of
+                                  floor(s^X m / |X|), P1 and fixed P2 scaled by m;
+                                  1 negated, truncated and scaled NCC (0..255 per view),
+                                  S = min over X of floor(s^X / |X|), penalties unscaled */
 } fassmvs_config;
 
 typedef struct {
@@ -232,6 +239,19 @@ fassmvs_status fassmvs_stage_cost(fassmvs_handle *h, int32_t w, int32_t hgt, con
                                   int32_t n_views, const uint8_t *const *views, const int8_t *view_side,
                                   int32_t cw, int32_t ch, int32_t n_fam, const int32_t *G, const int32_t *W,
                                   const double *H, const int32_t *offs, const float *warped, uint8_t *S);
+
+/* The NCC cost volume (Alg. 1 with the negated, truncated and scaled NCC of
+ * the similarity-measure section): for every pixel, label and view the
+ * cw x ch window of the reference image ref_img (caller-owned device
+ * memory, [h][w] uint8, replicate border) against the same window of the
+ * warped view; per view C = floor(255 min(1, 1 - rho) + 0.5) with rho the
+ * correlation coefficient (sums in double, 0 for a flat window); S = min
+ * over the non-empty subsets of the subset's mean cost.  Other arguments
+ * and errors as fassmvs_stage_cost; window sizes 3x3, 5x5, 7x7, 9x9. */
+fassmvs_status fassmvs_stage_cost_ncc(fassmvs_handle *h, int32_t w, int32_t hgt, const uint8_t *ref_img,
+                                      int32_t n_views, const uint8_t *const *views, const int8_t *view_side,
+                                      int32_t cw, int32_t ch, int32_t n_fam, const int32_t *G, const int32_t *W,
+                                      const double *H, const int32_t *offs, const float *warped, uint8_t *S);
 
 /* Semi-global aggregation and winner-takes-all (Eq. sgm-path, sgm-aggr,
  * sgm-wta with the smoothness terms of Eq. sgm-smooth-fp / sgm-smooth-sn).

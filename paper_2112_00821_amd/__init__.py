@@ -38,6 +38,7 @@ class Config(C.Structure):
         ("normal_radius", C.c_int32), ("normal_beta", C.c_double), ("conf_rho_deg", C.c_double),
         ("device", C.c_int32), ("stream", C.c_void_p), ("hbm_budget_bytes", C.c_uint64),
         ("profile", C.c_int32), ("keep_levels", C.c_int32), ("sgm_debug", C.c_int32),
+        ("cost", C.c_int32),
     ]
 
 
@@ -89,6 +90,7 @@ def _declare(L):
         "fassmvs_stage_census": (st, [vp, vp, i32, i32, i32, i32, vp]),
         "fassmvs_stage_warp": (st, [vp, vp, i32, i32, vp, i32, i32, vp]),
         "fassmvs_stage_cost": (st, [vp, i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "fassmvs_stage_cost_ncc": (st, [vp, i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "fassmvs_stage_sgm": (st, [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]),
         "fassmvs_stage_sgm_pg": (st, [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp,
                                       vp, vp]),
@@ -133,6 +135,7 @@ def config_from_params(params: dict, **kw) -> Config:
     for k in keys:
         if k in params:
             setattr(c, k, params[k])
+    c.cost = {"census": 0, "ncc": 1}[params.get("cost", "census")]
     for k, v in kw.items():
         setattr(c, k, v)
     return c
@@ -360,6 +363,19 @@ class Handle:
         Ha, Hp = _arr(H, np.float64)
         self._check(lib().fassmvs_stage_cost(self.h, w, h, ct_ref.vp, len(side), vptr, sd, cw, ch, len(Ga), Gp, Wp,
                                              Hp, _vp(offs), _vp(warped), out.vp))
+        return out
+
+    def stage_cost_ncc(self, ref_img: DeviceArray, views, side, cw, ch, G, W, H, offs=None, warped=None):
+        h, w = ref_img.shape
+        D = int(np.sum(W))
+        out = self.empty((h, w, D), np.uint8)
+        vptr = (C.c_void_p * len(side))(*[(v.ptr if v is not None else None) for v in (views or [None] * len(side))])
+        sd = (C.c_int8 * len(side))(*side)
+        Ga, Gp = _arr(G, np.int32)
+        Wa, Wp = _arr(W, np.int32)
+        Ha, Hp = _arr(H, np.float64)
+        self._check(lib().fassmvs_stage_cost_ncc(self.h, w, h, ref_img.vp, len(side), vptr, sd, cw, ch, len(Ga), Gp,
+                                                 Wp, Hp, _vp(offs), _vp(warped), out.vp))
         return out
 
     def stage_sgm(self, S: DeviceArray, W, p1, lut, ref: DeviceArray, n_paths, offs=None, dI=None,

@@ -1,9 +1,11 @@
 // Fused plane-sweep matching on gfx950 (Alg. 1 of the paper): for a tile of
 // reference pixels and each plane label, every matching view is warped onto
-// the tile (plus the census halo) into LDS, the census of the warped view is
-// formed in LDS, its Hamming distance to the reference census taken with
-// v_bcnt, the per-side sums combined by the occlusion-robust minimum, and
-// the cost written to the label-innermost uint8 volume S[y][x][label].
+// the tile (plus the window halo) into LDS; the matching cost of each pixel
+// is taken in LDS -- the census of the warped view and its Hamming distance
+// to the reference census (v_bcnt), or the negated, truncated and scaled
+// NCC against the reference window -- the per-side sums combined by the
+// occlusion-robust minimum, and the cost written to the label-innermost
+// uint8 volume S[y][x][label].
 //
 // Tile 64 x 32 pixels, 256 threads = 4 waves; thread (tx, ty) owns column
 // tx and rows 8ty..8ty+7, so every LDS row read serves up to eight census
@@ -27,6 +29,17 @@ __device__ __forceinline__ uint32_t insert_sign(uint32_t acc, float v, float c) 
     // (acc << 1) | [v < c]: the sign of v - c (exact for distinct floats,
     // +0 when equal) shifted in through alignbit
     return __builtin_amdgcn_alignbit(acc, __float_as_uint(v - c), 31);
+}
+
+// Subset mean for the NCC cost: min over non-empty X of floor(s^X / |X|).
+__device__ __forceinline__ int combine_mean(int sL, int sR, int nL, int nR) {
+    int best = INT_MAX;
+    if (nL > 0) best = sL / nL;
+    if (nR > 0) {
+        int v = sR / nR;
+        best = v < best ? v : best;
+    }
+    return best;
 }
 
 __device__ __forceinline__ int combine_lr(int sL, int sR, int nL, int nR, int m) {
@@ -66,7 +79,22 @@ __device__ __forceinline__ void warp_region(float *buf, const uint8_t *__restric
 }
 }  // namespace
 
-template <int CW, int CH, int RPT, bool WARPED>
+// NCC cost of one view at one pixel from its window sums (the oracle's
+// definition, the same operations in the same order): sA and vA = n sAA -
+// sA^2 are exact integers of the reference window.
+__device__ __forceinline__ int ncc_finish(int sA_i, int vA_i, double sB, double sBB, double sAB, double n) {
+    const double sA = (double)sA_i;
+    const double vA = (double)vA_i;
+    const double vB = n * sBB - sB * sB;
+    const double cov = n * sAB - sA * sB;
+    double rho = 0.0;
+    if (vA > 0.0 && vB > 0.0) rho = cov / sqrt(vA * vB);
+    rho = fmin(1.0, fmax(-1.0, rho));
+    const double c = fmin(1.0, 1.0 - rho);
+    return (int)floor(255.0 * c + 0.5);
+}
+
+template <int CW, int CH, int RPT, bool WARPED, int COST>
 __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
     constexpr int TH = 4 * RPT;
     constexpr int RX = CW / 2, RY = CH / 2;
@@ -75,6 +103,7 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
     constexpr int NHI = NB > 32 ? NB - 32 : 0;
     constexpr int NS = RW * RH;
     __shared__ float wbuf[2][NS];
+    __shared__ double aref[COST == 1 ? NS : 1];   // reference intensities of the region (NCC)
     __shared__ double tqx[RW], tqy[RH];
     __shared__ int s_lo[kMaxFam], s_hi[kMaxFam];
 
@@ -102,17 +131,38 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
     if (tid < RH) tqy[tid] = (double)min(max(y0 - RY + tid, 0), a.h - 1) + 0.5;
     __syncthreads();
 
-    uint32_t ref_hi[RPT], ref_lo[RPT];
+    uint32_t ref_hi[RPT], ref_lo[RPT];   // census cost: the reference census words
+    int refA[RPT], refV[RPT];            // NCC cost: sum and n * sum of squares - sum^2 of the window
     bool valid[RPT];
     uint32_t pix[RPT];
+    if (COST == 1) {
+        for (int s2 = tid; s2 < NS; s2 += NT) {
+            const int rx = s2 % RW, ry = s2 / RW;
+            const int qx = min(max(x0 - RX + rx, 0), a.w - 1), qy = min(max(y0 - RY + ry, 0), a.h - 1);
+            aref[s2] = (double)a.ref[(size_t)qy * a.w + qx];
+        }
+        __syncthreads();
+    }
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         int y = y0 + ty * RPT + j;
         valid[j] = x < a.w && y < a.h;
         pix[j] = valid[j] ? (uint32_t)(y * a.w + x) : 0u;
-        uint64_t ct = valid[j] ? a.ct_ref[pix[j]] : 0;
-        ref_hi[j] = (uint32_t)(ct >> 32);
-        ref_lo[j] = (uint32_t)ct;
+        if (COST == 0) {
+            uint64_t ct = valid[j] ? a.ct_ref[pix[j]] : 0;
+            ref_hi[j] = (uint32_t)(ct >> 32);
+            ref_lo[j] = (uint32_t)ct;
+        } else {
+            int sA = 0, sAA = 0;
+            for (int dy = 0; dy < CH; ++dy)
+                for (int dx = 0; dx < CW; ++dx) {
+                    const int v = (int)aref[(ty * RPT + j + dy) * RW + tx + dx];
+                    sA += v;
+                    sAA += v * v;
+                }
+            refA[j] = sA;
+            refV[j] = CW * CH * sAA - sA * sA;
+        }
         if (valid[j]) {
             for (int f = 0; f < a.n_fam; ++f) {
                 int o = a.offs ? a.offs[(size_t)f * N + pix[j]] : 0;
@@ -179,39 +229,83 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
                 warp_region<RW, NS>(buf, src, a.w, a.h, tqx, tqy, tid, h0, h1, h2, h3, h4, h5, h6, h7, h8);
             }
             __syncthreads();
-            // census of the warped view for this thread's four pixels
+            const bool left = a.side[k] < 0;
             const float *base = buf + (ty * RPT) * RW + tx;
-            float c[RPT];
+            if (COST == 0) {
+                // census of the warped view for this thread's pixels
+                float c[RPT];
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) c[j] = base[(j + RY) * RW + RX];
-            uint32_t hi[RPT], lo[RPT];
+                for (int j = 0; j < RPT; ++j) c[j] = base[(j + RY) * RW + RX];
+                uint32_t hi[RPT], lo[RPT];
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) hi[j] = lo[j] = 0;
+                for (int j = 0; j < RPT; ++j) hi[j] = lo[j] = 0;
 #pragma unroll
-            for (int rr = 0; rr < RPT + 2 * RY; ++rr) {
-                float v[CW];
+                for (int rr = 0; rr < RPT + 2 * RY; ++rr) {
+                    float v[CW];
 #pragma unroll
-                for (int cx = 0; cx < CW; ++cx) v[cx] = base[rr * RW + cx];
+                    for (int cx = 0; cx < CW; ++cx) v[cx] = base[rr * RW + cx];
 #pragma unroll
-                for (int j = 0; j < RPT; ++j) {
-                    const int wy = rr - j;
-                    if (wy < 0 || wy >= CH) continue;
+                    for (int j = 0; j < RPT; ++j) {
+                        const int wy = rr - j;
+                        if (wy < 0 || wy >= CH) continue;
 #pragma unroll
-                    for (int cx = 0; cx < CW; ++cx) {
-                        if (wy == RY && cx == RX) continue;
-                        const int bpos = wy * CW + cx - ((wy > RY || (wy == RY && cx > RX)) ? 1 : 0);
-                        if (bpos < NHI)
-                            hi[j] = insert_sign(hi[j], v[cx], c[j]);
-                        else
-                            lo[j] = insert_sign(lo[j], v[cx], c[j]);
+                        for (int cx = 0; cx < CW; ++cx) {
+                            if (wy == RY && cx == RX) continue;
+                            const int bpos = wy * CW + cx - ((wy > RY || (wy == RY && cx > RX)) ? 1 : 0);
+                            if (bpos < NHI)
+                                hi[j] = insert_sign(hi[j], v[cx], c[j]);
+                            else
+                                lo[j] = insert_sign(lo[j], v[cx], c[j]);
+                        }
                     }
                 }
-            }
-            const bool left = a.side[k] < 0;
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                int cst = __popc(hi[j] ^ ref_hi[j]) + __popc(lo[j] ^ ref_lo[j]);
-                if (left) sL[j] += cst; else sR[j] += cst;
+                for (int j = 0; j < RPT; ++j) {
+                    int cst = __popc(hi[j] ^ ref_hi[j]) + __popc(lo[j] ^ ref_lo[j]);
+                    if (left) sL[j] += cst; else sR[j] += cst;
+                }
+            } else {
+                // NCC: row sums of the window rows, left to right, then the
+                // window sums over the rows top to bottom, in double
+                const double *abase = aref + (ty * RPT) * RW + tx;
+                double wB[RPT], wBB[RPT], wAB[RPT];
+#pragma unroll
+                for (int rr = 0; rr < RPT + 2 * RY; ++rr) {
+                    double rB = 0.0, rBB = 0.0, rAB = 0.0;
+#pragma unroll
+                    for (int cx = 0; cx < CW; ++cx) {
+                        const double vb = (double)base[rr * RW + cx];
+                        const double va = abase[rr * RW + cx];
+                        if (cx == 0) {
+                            rB = vb;
+                            rBB = vb * vb;
+                            rAB = va * vb;
+                        } else {
+                            rB = rB + vb;
+                            rBB = __builtin_fma(vb, vb, rBB);
+                            rAB = __builtin_fma(va, vb, rAB);
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < RPT; ++j) {
+                        const int wy = rr - j;
+                        if (wy < 0 || wy >= CH) continue;
+                        if (wy == 0) {
+                            wB[j] = rB;
+                            wBB[j] = rBB;
+                            wAB[j] = rAB;
+                        } else {
+                            wB[j] = wB[j] + rB;
+                            wBB[j] = wBB[j] + rBB;
+                            wAB[j] = wAB[j] + rAB;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) {
+                    const int cst = ncc_finish(refA[j], refV[j], wB[j], wBB[j], wAB[j], (double)(CW * CH));
+                    if (left) sL[j] += cst; else sR[j] += cst;
+                }
             }
         }
         // store the combined cost where this label lies in the pixel's window
@@ -219,7 +313,8 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
         for (int j = 0; j < RPT; ++j) {
             const int o = off[j];
             if (valid[j] && g >= o && g < o + a.W[f]) {
-                const uint32_t cst = (uint32_t)combine_lr(sL[j], sR[j], a.nL, a.nR, a.m);
+                const uint32_t cst = COST == 0 ? (uint32_t)combine_lr(sL[j], sR[j], a.nL, a.nR, a.m)
+                                               : (uint32_t)combine_mean(sL[j], sR[j], a.nL, a.nR);
                 const int idx = a.foff[f] + (g - o);
                 uint8_t *dst = a.S + (size_t)pix[j] * a.D + idx;
                 if (pack) {
@@ -256,8 +351,9 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
 hipError_t launch_sweep(const SweepArgs &a0, hipStream_t s) {
     SweepArgs a = a0;
     // rows per thread (tile height / 4): 8 halves the halo and the LDS reads
-    // per pixel, 4 keeps more waves resident
-    int rpt = a.rows_per_thread == 4 ? 4 : 8;
+    // per pixel, 4 keeps more waves resident (the NCC's double-precision
+    // window sums take many registers: 4 unless asked otherwise)
+    int rpt = a.rows_per_thread == 4 ? 4 : (a.rows_per_thread == 8 ? 8 : (a.cost == 1 ? 4 : 8));
     const int th = 4 * rpt;
     a.tiles_x = (a.w + TW - 1) / TW;
     a.tiles_y = (a.h + th - 1) / th;
@@ -270,21 +366,25 @@ hipError_t launch_sweep(const SweepArgs &a0, hipStream_t s) {
         a.n_chunks = want < 1 ? 1 : (want > maxc ? maxc : want);
     }
     dim3 grid((unsigned)(tiles * a.n_chunks));
-#define FMVS_SWEEP_RW(CWv, CHv, R)                                                               \
+#define FMVS_SWEEP_RW(CWv, CHv, R, C)                                                            \
     if (a.warped)                                                                                \
-        hipLaunchKernelGGL((k_sweep<CWv, CHv, R, true>), grid, dim3(NT), 0, s, a);               \
+        hipLaunchKernelGGL((k_sweep<CWv, CHv, R, true, C>), grid, dim3(NT), 0, s, a);            \
     else                                                                                         \
-        hipLaunchKernelGGL((k_sweep<CWv, CHv, R, false>), grid, dim3(NT), 0, s, a);
-#define FMVS_SWEEP(CWv, CHv)                                                                     \
-    if (a.cw == CWv && a.ch == CHv) {                                                            \
-        if (rpt == 4) { FMVS_SWEEP_RW(CWv, CHv, 4) }                                             \
-        else { FMVS_SWEEP_RW(CWv, CHv, 8) }                                                      \
+        hipLaunchKernelGGL((k_sweep<CWv, CHv, R, false, C>), grid, dim3(NT), 0, s, a);
+#define FMVS_SWEEP(CWv, CHv, C)                                                                  \
+    if (a.cost == C && a.cw == CWv && a.ch == CHv) {                                             \
+        if (rpt == 4) { FMVS_SWEEP_RW(CWv, CHv, 4, C) }                                          \
+        else { FMVS_SWEEP_RW(CWv, CHv, 8, C) }                                                   \
         return hipGetLastError();                                                                \
     }
-    FMVS_SWEEP(5, 5)
-    FMVS_SWEEP(9, 7)
-    FMVS_SWEEP(7, 7)
-    FMVS_SWEEP(3, 3)
+    FMVS_SWEEP(5, 5, 0)
+    FMVS_SWEEP(9, 7, 0)
+    FMVS_SWEEP(7, 7, 0)
+    FMVS_SWEEP(3, 3, 0)
+    FMVS_SWEEP(5, 5, 1)
+    FMVS_SWEEP(9, 9, 1)
+    FMVS_SWEEP(7, 7, 1)
+    FMVS_SWEEP(3, 3, 1)
 #undef FMVS_SWEEP_RW
 #undef FMVS_SWEEP
     return hipErrorInvalidValue;

@@ -30,7 +30,9 @@ struct SweepArgs {
     int n_views, nL, nR, m;
     const uint8_t *views[kMaxViews];
     int side[kMaxViews];
-    const uint64_t *ct_ref;   // [h][w]
+    int cost;                 // 0: census-Hamming, 1: NCC
+    const uint64_t *ct_ref;   // [h][w] reference census (census cost)
+    const uint8_t *ref;       // [h][w] reference image (NCC cost)
     int n_fam, D, sumG;
     int G[kMaxFam], W[kMaxFam], foff[kMaxFam], goff[kMaxFam];
     const double *H;          // [n_views][sumG][9]

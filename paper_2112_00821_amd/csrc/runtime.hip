@@ -297,10 +297,16 @@ fassmvs_status validate_config(const fassmvs_config *c, std::string &msg) {
         msg = "census window must be odd";
         return FASSMVS_EINVAL;
     }
-    if (c->census_w * c->census_h - 1 > 64) { msg = "census window exceeds 64 bits"; return FASSMVS_EINVAL; }
-    bool ok_cw = (c->census_w == 5 && c->census_h == 5) || (c->census_w == 9 && c->census_h == 7) ||
-                 (c->census_w == 7 && c->census_h == 7) || (c->census_w == 3 && c->census_h == 3);
-    if (!ok_cw) { msg = "census window not built (3x3, 5x5, 7x7, 9x7)"; return FASSMVS_EUNSUPPORTED; }
+    if (c->cost != 0 && c->cost != 1) { msg = "cost must be 0 (census) or 1 (NCC)"; return FASSMVS_EINVAL; }
+    if (c->cost == 0) {
+        if (c->census_w * c->census_h - 1 > 64) { msg = "census window exceeds 64 bits"; return FASSMVS_EINVAL; }
+        bool ok_cw = (c->census_w == 5 && c->census_h == 5) || (c->census_w == 9 && c->census_h == 7) ||
+                     (c->census_w == 7 && c->census_h == 7) || (c->census_w == 3 && c->census_h == 3);
+        if (!ok_cw) { msg = "census window not built (3x3, 5x5, 7x7, 9x7)"; return FASSMVS_EUNSUPPORTED; }
+    } else {
+        bool ok_nw = c->census_w == c->census_h && c->census_w >= 3 && c->census_w <= 9;
+        if (!ok_nw) { msg = "NCC window not built (3x3, 5x5, 7x7, 9x9)"; return FASSMVS_EUNSUPPORTED; }
+    }
     if (c->n_paths != 4 && c->n_paths != 8) { msg = "n_paths must be 4 or 8"; return FASSMVS_EINVAL; }
     if (c->sgm_variant < 0 || c->sgm_variant > 2) { msg = "sgm_variant must be 0, 1 or 2"; return FASSMVS_EINVAL; }
     if (c->p1 < 0 || c->p1 > 4096) { msg = "p1 out of range"; return FASSMVS_EINVAL; }
@@ -352,8 +358,12 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
         P.side[k] = side[k];
     }
     P.m = std::max(P.nL, P.nR);
-    const int nbits = c.census_w * c.census_h - 1;
-    if (P.m * nbits > 255) return fail(h, FASSMVS_EUNSUPPORTED, "matching cost exceeds 8 bits (m * census bits > 255)");
+    // cost bound of S and the penalty scale: the census sum over a subset is
+    // scaled to m views; the NCC subset mean stays on one view's 0..255
+    const int nbits = c.cost == 0 ? c.census_w * c.census_h - 1 : 255;
+    const int mpen = c.cost == 0 ? P.m : 1;
+    if (c.cost == 0 && P.m * nbits > 255)
+        return fail(h, FASSMVS_EUNSUPPORTED, "matching cost exceeds 8 bits (m * census bits > 255)");
     if (!(std::fabs(K[0]) > 0) || K[3] != 0.0 || K[6] != 0.0 || K[7] != 0.0 || K[8] != 1.0 || !finite_all(K, 9))
         return fail(h, FASSMVS_EINVAL, "K must be upper triangular with K[8] = 1");
     // relative poses and camera centres in reference coordinates
@@ -378,17 +388,17 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
                 return fail(h, FASSMVS_EINVAL, "a camera centre lies behind the nearest sweep plane");
         }
     }
-    // penalties: P1 and P2 scaled by the subset size m
-    P.p1 = P.m * c.p1;
+    // penalties: P1 and P2 scaled like the cost
+    P.p1 = mpen * c.p1;
     int p2max = 0;
     for (int i = 0; i < 256; ++i) {
         if (c.p2_mode == 0)
-            P.lut[i] = P.m * c.p2_fixed;
+            P.lut[i] = mpen * c.p2_fixed;
         else
             P.lut[i] = (int)std::floor((double)P.p1 * (1.0 + c.p2_alpha * std::exp(-(double)i / c.p2_beta)) + 0.5);
         p2max = std::max(p2max, P.lut[i]);
     }
-    if ((long)c.n_paths * ((long)P.m * nbits + p2max) > 65535)
+    if ((long)c.n_paths * ((long)mpen * nbits + p2max) > 65535)
         return fail(h, FASSMVS_EUNSUPPORTED, "aggregated cost could exceed 16 bits; lower P1/P2 or views");
     // levels
     size_t hsz = 0, dsz = 0;
@@ -601,7 +611,7 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
         const size_t N = (size_t)L.w * L.h;
         auto &B = h->lb[l];
         const uint8_t *ref = (const uint8_t *)h->pyr[0].p + lvl_off[l];
-        {
+        if (c.cost == 0) {
             Timer t(h, ST_CENSUS);
             HIPCHK(h, launch_census(ref, L.w, L.h, c.census_w, c.census_h, (uint64_t *)h->ct.p, h->stream), "census");
         }
@@ -623,7 +633,9 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
                 a.views[k] = (const uint8_t *)h->pyr[k + 1].p + lvl_off[l];
                 a.side[k] = P.side[k];
             }
+            a.cost = c.cost;
             a.ct_ref = (const uint64_t *)h->ct.p;
+            a.ref = ref;
             a.n_fam = L.F;
             a.D = L.D;
             a.sumG = L.sumG;
@@ -1130,12 +1142,13 @@ fassmvs_status fassmvs_stage_warp(fassmvs_handle *h, const uint8_t *src, int32_t
     STAGE_END;
 }
 
-fassmvs_status fassmvs_stage_cost(fassmvs_handle *h, int32_t w, int32_t hgt, const uint64_t *ct_ref, int32_t n_views,
-                                  const uint8_t *const *views, const int8_t *view_side, int32_t cw, int32_t ch,
-                                  int32_t n_fam, const int32_t *G, const int32_t *W, const double *H,
-                                  const int32_t *offs, const float *warped, uint8_t *S) {
-    STAGE_BEGIN;
-    if (!ct_ref || !views || !view_side || !G || !W || !H || !S || w < 1 || hgt < 1)
+namespace {
+fassmvs_status stage_cost_any(fassmvs_handle *h, int cost, int32_t w, int32_t hgt, const uint64_t *ct_ref,
+                              const uint8_t *ref_img, int32_t n_views, const uint8_t *const *views,
+                              const int8_t *view_side, int32_t cw, int32_t ch, int32_t n_fam, const int32_t *G,
+                              const int32_t *W, const double *H, const int32_t *offs, const float *warped,
+                              uint8_t *S) {
+    if ((cost == 0 ? !ct_ref : !ref_img) || !views || !view_side || !G || !W || !H || !S || w < 1 || hgt < 1)
         return fail(h, FASSMVS_EINVAL, "bad cost arguments");
     if (n_views < 1 || n_views > kMaxViews || n_fam < 1 || n_fam > kMaxFam) return fail(h, FASSMVS_EINVAL, "bad counts");
     SweepArgs a;
@@ -1144,15 +1157,17 @@ fassmvs_status fassmvs_stage_cost(fassmvs_handle *h, int32_t w, int32_t hgt, con
     a.h = hgt;
     a.cw = cw;
     a.ch = ch;
+    a.cost = cost;
     a.n_views = n_views;
     for (int k = 0; k < n_views; ++k) {
         if (!views[k] && !warped) return fail(h, FASSMVS_EINVAL, "null view");
+        if (view_side[k] != -1 && view_side[k] != 1) return fail(h, FASSMVS_EINVAL, "view_side must be -1 or +1");
         a.views[k] = views[k];
         a.side[k] = view_side[k];
         if (view_side[k] < 0) a.nL++; else a.nR++;
     }
     a.m = std::max(a.nL, a.nR);
-    if (a.m * (cw * ch - 1) > 255) return fail(h, FASSMVS_EUNSUPPORTED, "cost exceeds 8 bits");
+    if (cost == 0 && a.m * (cw * ch - 1) > 255) return fail(h, FASSMVS_EUNSUPPORTED, "cost exceeds 8 bits");
     a.n_fam = n_fam;
     for (int f = 0; f < n_fam; ++f) {
         if (W[f] < 1 || W[f] > G[f] || (!offs && W[f] != G[f])) return fail(h, FASSMVS_EINVAL, "bad family sizes");
@@ -1171,13 +1186,38 @@ fassmvs_status fassmvs_stage_cost(fassmvs_handle *h, int32_t w, int32_t hgt, con
     HIPCHK(h, hipStreamSynchronize(h->stream), "H upload");
     a.H = (const double *)h->params.p;
     a.ct_ref = ct_ref;
+    a.ref = ref_img;
     a.offs = offs;
     a.warped = warped;
     a.S = S;
     a.rows_per_thread = sweep_rows();
     hipError_t e = launch_sweep(a, h->stream);
-    if (e == hipErrorInvalidValue) return fail(h, FASSMVS_EUNSUPPORTED, "census window not built");
+    if (e == hipErrorInvalidValue) return fail(h, FASSMVS_EUNSUPPORTED, "matching window not built");
     HIPCHK(h, e, "sweep launch");
+    return FASSMVS_OK;
+}
+}  // namespace
+
+fassmvs_status fassmvs_stage_cost(fassmvs_handle *h, int32_t w, int32_t hgt, const uint64_t *ct_ref, int32_t n_views,
+                                  const uint8_t *const *views, const int8_t *view_side, int32_t cw, int32_t ch,
+                                  int32_t n_fam, const int32_t *G, const int32_t *W, const double *H,
+                                  const int32_t *offs, const float *warped, uint8_t *S) {
+    STAGE_BEGIN;
+    fassmvs_status st = stage_cost_any(h, 0, w, hgt, ct_ref, nullptr, n_views, views, view_side, cw, ch, n_fam, G, W,
+                                       H, offs, warped, S);
+    if (st != FASSMVS_OK) return st;
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_stage_cost_ncc(fassmvs_handle *h, int32_t w, int32_t hgt, const uint8_t *ref_img,
+                                      int32_t n_views, const uint8_t *const *views, const int8_t *view_side,
+                                      int32_t cw, int32_t ch, int32_t n_fam, const int32_t *G, const int32_t *W,
+                                      const double *H, const int32_t *offs, const float *warped, uint8_t *S) {
+    STAGE_BEGIN;
+    if (cw != ch) return fail(h, FASSMVS_EUNSUPPORTED, "NCC windows are square");
+    fassmvs_status st = stage_cost_any(h, 1, w, hgt, nullptr, ref_img, n_views, views, view_side, cw, ch, n_fam, G,
+                                       W, H, offs, warped, S);
+    if (st != FASSMVS_OK) return st;
     STAGE_END;
 }
 

@@ -548,7 +548,20 @@ WORKLOADS = {
     "config2_ragged": lambda: config2(5, 333, 187, planes=32, window=16),
     "config3_small": lambda: config3(2, 320, 180, planes=16, window=16),
     "nadir_planar": lambda: nadir_planar(7),
+    # the NCC matching cost (5x5 window, phi1 = 100 as in the paper's NCC
+    # experiments; fixed P2 of config 1 scaled the same way)
+    "config1_ncc": lambda: with_ncc(config1(0), p2_fixed=400),
+    "config2_small_ncc": lambda: with_ncc(config2(1, 320, 184, planes=32, window=32)),
+    "config2_ncc": lambda: with_ncc(config2(1)),
 }
+
+
+def with_ncc(wl, window: int = 5, p1: int = 100, p2_fixed: int | None = None):
+    """The same bundle matched with the negated, truncated and scaled NCC."""
+    params = dict(wl["params"], cost="ncc", census_w=window, census_h=window, p1=p1)
+    if p2_fixed is not None:
+        params["p2_fixed"] = p2_fixed
+    return dict(wl, params=params)
 
 
 def make_workload(name: str, cache_dir: str | None = None):

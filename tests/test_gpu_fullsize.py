@@ -4,7 +4,8 @@
   SGM^Pi-sn 8 paths (the benchmark workload);
 * 2704x1520, 4 views, 4 plane families (fronto-parallel, ground, ground
   tilted by +-20 degrees) x 96 planes per level (384 labels), census 9x7,
-  SGM^Pi-sn 8 paths.
+  SGM^Pi-sn 8 paths;
+* the 1920x1080 workload matched with the 5x5 NCC cost.
 
 Checked:
 
@@ -27,7 +28,22 @@ import scenegen
 
 pytestmark = pytest.mark.gpu
 
-WORKLOADS = ["config2", "config3"]
+WORKLOADS = ["config2", "config3", "config2_ncc"]
+
+
+def _ncc(wl):
+    return wl["params"].get("cost", "census") == "ncc"
+
+
+def _cost_pixels(orc, wl, img, views, plan, H, xy, offs=None):
+    """Oracle cost vectors of sampled pixels with the workload's cost."""
+    p = wl["params"]
+    if _ncc(wl):
+        return orc.ncc_cost_pixels(img, views, wl["side"], p["census_w"], p["census_h"], plan["G"], plan["W"], H, xy,
+                                   offs=offs)
+    ct = orc.census(img, p["census_w"], p["census_h"])
+    return orc.cost_pixels(ct, views, wl["side"], p["census_w"], p["census_h"], plan["G"], plan["W"], H, xy,
+                           offs=offs)
 
 
 @pytest.fixture(scope="module", params=WORKLOADS)
@@ -57,7 +73,8 @@ def test_pyramid_and_census_bit_exact(orc, run):
             assert np.array_equal(h.level_map(l, 30 + i), cur), (i, l)
             if l < n - 1:
                 cur = orc.pyr_down(cur)
-    assert np.array_equal(h.level_map(0, 20), orc.census(wl["ref"]["img"], 9, 7))
+    if not _ncc(wl):
+        assert np.array_equal(h.level_map(0, 20), orc.census(wl["ref"]["img"], 9, 7))
 
 
 def _views_at(orc, wl, level):
@@ -111,17 +128,21 @@ def test_coarsest_level(orc, run):
     # points recompute them from the pipeline's own pyramid)
     Ki, plan, H = _level(orc, wl, top)
     img, views = _views_at(orc, wl, top)
+    p = wl["params"]
+    cw, ch = p["census_w"], p["census_h"]
     assert np.array_equal(h.level_map(top, 30), img)
-    ctd = h.stage_census(h.upload(h.level_map(top, 30)), 9, 7)
     vd = [h.upload(h.level_map(top, 31 + k)) for k in range(len(views))]
-    S = h.stage_cost(ctd, vd, wl["side"], 9, 7, plan["G"], plan["W"], H).numpy()
+    if _ncc(wl):
+        S = h.stage_cost_ncc(h.upload(img), vd, wl["side"], cw, ch, plan["G"], plan["W"], H).numpy()
+    else:
+        ctd = h.stage_census(h.upload(h.level_map(top, 30)), cw, ch)
+        assert np.array_equal(ctd.numpy(), orc.census(img, cw, ch))
+        S = h.stage_cost(ctd, vd, wl["side"], cw, ch, plan["G"], plan["W"], H).numpy()
     hh, ww = S.shape[:2]
     rng = np.random.default_rng(5)
     xy = np.stack([rng.integers(0, ww, 300), rng.integers(0, hh, 300)], -1)
     xy = np.concatenate([xy, [[0, 0], [ww - 1, hh - 1], [ww - 1, 0], [0, hh - 1]]]).astype(np.int32)
-    ct = orc.census(img, 9, 7)
-    assert np.array_equal(ctd.numpy(), ct)
-    exp = orc.cost_pixels(ct, views, wl["side"], 9, 7, plan["G"], plan["W"], H, xy)
+    exp = _cost_pixels(orc, wl, img, views, plan, H, xy)
     got = S[xy[:, 1], xy[:, 0]]
     assert np.mean(got == exp) >= 0.9999
     assert np.max(np.abs(got.astype(int) - exp.astype(int))) <= 2
@@ -149,9 +170,7 @@ def test_level0_cost_samples(orc, run):
     hh, ww = S.shape[:2]
     xy = np.stack([rng.integers(0, ww, 400), rng.integers(0, hh, 400)], -1)
     xy = np.concatenate([xy, [[0, 0], [ww - 1, hh - 1], [ww - 1, 0], [0, hh - 1]]])
-    ct = orc.census(wl["ref"]["img"], 9, 7)
-    exp = orc.cost_pixels(ct, [v["img"] for v in wl["views"]], wl["side"], 9, 7, plan["G"], plan["W"], H, xy,
-                          offs=offs)
+    exp = _cost_pixels(orc, wl, wl["ref"]["img"], [v["img"] for v in wl["views"]], plan, H, xy, offs=offs)
     got = S[xy[:, 1], xy[:, 0]]
     assert np.mean(got == exp) >= 0.9999
     assert np.max(np.abs(got.astype(int) - exp.astype(int))) <= 2
@@ -191,16 +210,14 @@ def test_level0_path_costs(orc, run, r, which):
     xy = _path_pixels(r, which, ww, hh, orc.DIRS)
     offs = h.level_map(0, 6, n_fam=nf)
     dI = h.level_map(0, 7, n_fam=nf)
-    ct = orc.census(wl["ref"]["img"], 9, 7)
-    Sp = orc.cost_pixels(ct, [v["img"] for v in wl["views"]], wl["side"], 9, 7, plan["G"], plan["W"], H, xy,
-                         offs=offs)
+    Sp = _cost_pixels(orc, wl, wl["ref"]["img"], [v["img"] for v in wl["views"]], plan, H, xy, offs=offs)
     n = len(xy)
     strip_S = Sp.reshape(n, 1, D)
     strip_offs = offs[:, xy[:, 1], xy[:, 0]].reshape(nf, n, 1)
     strip_dI = np.zeros((8, n, 1, nf), np.int8)
     strip_dI[2] = dI[r, xy[:, 1], xy[:, 0], :].reshape(n, 1, nf)
     ref = wl["ref"]["img"][xy[:, 1], xy[:, 0]].reshape(n, 1)
-    m = orc.subset_multiplier(wl["side"])
+    m = 1 if _ncc(wl) else orc.subset_multiplier(wl["side"])
     p = wl["params"]
     lut = orc.p2_lut(m * p["p1"], p["p2_mode"], m * p["p2_fixed"], p["p2_alpha"], p["p2_beta"])
     _, Lr = orc.sgm(strip_S, plan["W"], m * p["p1"], lut, ref, 4, offs=strip_offs, dI=strip_dI,

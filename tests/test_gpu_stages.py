@@ -284,3 +284,68 @@ def test_sgm_random_volumes(orc, hd, monkeypatch, kernel, shape, W, G, paths):
     assert np.array_equal(r["Lr"].numpy(), Lr)
     assert np.array_equal(r["Sbar"].numpy(), Sbar)
     assert np.array_equal(r["wta"].numpy(), np.argmin(Sbar, axis=-1))
+
+
+@pytest.mark.parametrize("name", ["config1_ncc", "config2_small_ncc"])
+def test_ncc_cost_from_oracle_warps_bit_exact(orc, hd, name):
+    """NCC window sums, square root, scaling and the subset mean are
+    bit-exact when the kernel is fed the oracle's warped images."""
+    wl = scenegen.make_workload(name)
+    p = wl["params"]
+    level = p["n_levels"] - 1
+    out = orc.run_frame(wl, keep=True, levels_only=level)
+    lv = out["levels"][level]
+    Ki, Kl, plan, H = _level_inputs(orc, wl, level)
+    views = [pv[level] for pv in out["pyr_views"]]
+    h, w = lv["img"].shape
+    warped = np.zeros((len(views), sum(plan["G"]), h, w), np.float32)
+    for k in range(len(views)):
+        for g in range(sum(plan["G"])):
+            warped[k, g] = orc.warp(views[k], H[k, g], w, h)
+    got = hd.stage_cost_ncc(hd.upload(lv["img"]), None, wl["side"], p["census_w"], p["census_h"], plan["G"],
+                            plan["W"], H, warped=hd.upload(warped)).numpy()
+    assert np.array_equal(got, lv["S"])
+
+
+@pytest.mark.parametrize("name", ["config1_ncc", "config2_small_ncc"])
+@pytest.mark.parametrize("rows", ["4", "8"])
+def test_ncc_cost_volume_from_images(orc, hd, monkeypatch, name, rows):
+    monkeypatch.setenv("FASSMVS_SWEEP_ROWS", rows)
+    wl = scenegen.make_workload(name)
+    p = wl["params"]
+    level = p["n_levels"] - 1
+    out = orc.run_frame(wl, keep=True, levels_only=level)
+    lv = out["levels"][level]
+    Ki, Kl, plan, H = _level_inputs(orc, wl, level)
+    views = [hd.upload(pv[level]) for pv in out["pyr_views"]]
+    got = hd.stage_cost_ncc(hd.upload(lv["img"]), views, wl["side"], p["census_w"], p["census_h"], plan["G"],
+                            plan["W"], H).numpy()
+    eq = got == lv["S"]
+    assert eq.mean() >= 0.9999, eq.mean()
+    assert np.max(np.abs(got.astype(int) - lv["S"].astype(int))) <= 3
+
+
+@pytest.mark.parametrize("n", [3, 7, 9])
+def test_ncc_window_sizes_bit_exact(orc, hd, n):
+    """3x3, 7x7 and 9x9 NCC windows on random views and random homographies
+    near the identity, with offsets (dynamic windows), from the oracle's
+    warped images."""
+    rng = np.random.default_rng(n)
+    h, w = 45, 70
+    ref = rng.integers(0, 256, (h, w)).astype(np.uint8)
+    views = [rng.integers(0, 256, (h, w)).astype(np.uint8) for _ in range(3)]
+    side = [-1, 1, 1]
+    G, W = [12, 6], [5, 6]
+    H = np.zeros((3, sum(G), 3, 3))
+    for k in range(3):
+        for g in range(sum(G)):
+            H[k, g] = np.eye(3) + rng.normal(0, 0.002, (3, 3)) * np.array([[1, 1, 50], [1, 1, 50], [0.001, 0.001, 1]])
+    offs = np.stack([rng.integers(0, g - wf + 1, (h, w)) for g, wf in zip(G, W)]).astype(np.int32)
+    warped = np.zeros((3, sum(G), h, w), np.float32)
+    for k in range(3):
+        for g in range(sum(G)):
+            warped[k, g] = orc.warp(views[k], H[k, g], w, h)
+    exp = orc.ncc_cost_volume(ref, views, side, n, n, G, W, H, offs)
+    got = hd.stage_cost_ncc(hd.upload(ref), None, side, n, n, G, W, H, offs=hd.upload(offs),
+                            warped=hd.upload(warped)).numpy()
+    assert np.array_equal(got, exp)
