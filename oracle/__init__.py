@@ -82,6 +82,11 @@ def _declare(L):
         "or_upsample_nn": (None, [vp, i, i, i, i, i, vp]),
         "or_window_offsets": (None, [vp, i, i, vp, i, vp, vp, vp, vp, vp, vp]),
         "or_delta_i": (None, [vp, vp, i, i, vp, i, vp, vp, vp]),
+        "or_gauss_taps": (None, [d, i, vp]),
+        "or_dog": (None, [vp, i, i, d, i, vp]),
+        "or_dog_mask": (None, [vp, i, i, d, i, d, i, i, vp]),
+        "or_speckle": (None, [vp, i, i, i, i]),
+        "or_geo_consistency": (None, [i, i, vp, vp, i, vp, vp, vp, d, i, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -466,3 +471,52 @@ def run_frame(wl, keep=False, levels_only=None):
     out["pyr_ref"] = pyr_ref
     out["pyr_views"] = pyr_views
     return out
+
+
+# ----------------------------------------------------------------- post filters
+DOG_SIGMA, DOG_RADIUS, DOG_THRESH, DOG_MIN_ON, DOG_MIN_OFF = 1.4, 3, 0.5, 7, 21
+
+
+def gauss_taps(sigma=DOG_SIGMA, radius=DOG_RADIUS):
+    t = np.zeros(2 * radius + 1)
+    lib().or_gauss_taps(float(sigma), int(radius), _p(t))
+    return t
+
+
+def dog(img, sigma=DOG_SIGMA, radius=DOG_RADIUS):
+    img = _c(img, np.uint8)
+    h, w = img.shape
+    out = np.zeros((h, w))
+    lib().or_dog(_p(img), w, h, float(sigma), int(radius), _p(out))
+    return out
+
+
+def dog_mask(img, sigma=DOG_SIGMA, radius=DOG_RADIUS, thresh=DOG_THRESH, min_on=DOG_MIN_ON, min_off=DOG_MIN_OFF):
+    """Texture mask of the DoG filter: 1 textured (keep), 0 weak texture."""
+    img = _c(img, np.uint8)
+    h, w = img.shape
+    m = np.zeros((h, w), np.uint8)
+    lib().or_dog_mask(_p(img), w, h, float(sigma), int(radius), float(thresh), int(min_on), int(min_off), _p(m))
+    return m
+
+
+def speckle(mask, value, min_size):
+    m = _c(mask, np.uint8).copy()
+    h, w = m.shape
+    lib().or_speckle(_p(m), w, h, int(value), int(min_size))
+    return m
+
+
+def geo_consistency(K, depth_ref, depth_nb, R, t, eta_r=10.0, eta_h=3):
+    """Hits and keep mask of the geometric consistency filter; R, t:
+    reference-to-neighbour relative poses [n][3][3], [n][3]."""
+    dref = _c(depth_ref, np.float32)
+    h, w = dref.shape
+    arrs = [_c(d, np.float32) for d in depth_nb]
+    ptrs = (C.c_void_p * max(len(arrs), 1))(*[a.ctypes.data for a in arrs])
+    hits = np.zeros((h, w), np.int32)
+    keep = np.zeros((h, w), np.uint8)
+    lib().or_geo_consistency(w, h, _p(_c(K, np.float64)), _p(dref), len(arrs), C.cast(ptrs, C.c_void_p),
+                             _p(_c(R, np.float64)), _p(_c(t, np.float64)), float(eta_r), int(eta_h), _p(hits),
+                             _p(keep))
+    return hits, keep

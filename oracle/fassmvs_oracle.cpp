@@ -942,3 +942,166 @@ void or_delta_i(const float* dbar, const float* nbar, int w, int h, const double
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Post-processing (Sec. on post-processing and depth map filtering).
+//
+// DoG texture mask (Alg. 3), with the readings: the 7x7 Gaussian has
+// sigma = 0.3 ((7 - 1)/2 - 1) + 0.8 = 1.4 (the usual rule for a kernel size
+// without a given sigma), taps exp(-i^2 / (2 sigma^2)) normalised to sum 1,
+// separable, replicate border, horizontal pass then vertical, each sum
+// accumulated from the first tap in double; DoG = I - I_smooth on the 0..255
+// scale; a pixel is active when |DoG| > 0.5; activation areas (4-connected)
+// of fewer than min_on pixels are cleared, the mask is dilated with a 3x3
+// square, deactivation areas of fewer than min_off pixels are filled.  The
+// result marks textured pixels (1); estimates where it is 0 (weakly
+// textured) are invalidated -- the stated purpose of the filter, where the
+// printed algorithm writes the opposite value.
+// ---------------------------------------------------------------------------
+namespace {
+// 4-connected components of the pixels equal to v; those with fewer than
+// min_size pixels flip to 1 - v.  Plain breadth-first search.
+void speckle(std::vector<uint8_t>& m, int w, int h, uint8_t v, int min_size) {
+    std::vector<int> comp((size_t)w * h, -1);
+    std::vector<int> queue;
+    for (int s = 0; s < w * h; ++s) {
+        if (m[s] != v || comp[s] >= 0) continue;
+        queue.clear();
+        queue.push_back(s);
+        comp[s] = s;
+        for (size_t qi = 0; qi < queue.size(); ++qi) {
+            int c = queue[qi], x = c % w, y = c / w;
+            const int nx[4] = {x - 1, x + 1, x, x};
+            const int ny[4] = {y, y, y - 1, y + 1};
+            for (int d = 0; d < 4; ++d) {
+                if (nx[d] < 0 || nx[d] >= w || ny[d] < 0 || ny[d] >= h) continue;
+                int n = ny[d] * w + nx[d];
+                if (m[n] == v && comp[n] < 0) {
+                    comp[n] = s;
+                    queue.push_back(n);
+                }
+            }
+        }
+        if ((int)queue.size() < min_size)
+            for (int c : queue) m[c] = (uint8_t)(1 - v);
+    }
+}
+}  // namespace
+
+extern "C" {
+
+void or_gauss_taps(double sigma, int radius, double* taps) {
+    double sum = 0.0;
+    for (int i = -radius; i <= radius; ++i) {
+        taps[i + radius] = std::exp(-(double)(i * i) / (2.0 * sigma * sigma));
+        sum += taps[i + radius];
+    }
+    for (int i = 0; i <= 2 * radius; ++i) taps[i] /= sum;
+}
+
+// DoG of the reference image (double, [h][w]) with the separable Gaussian.
+void or_dog(const uint8_t* img, int w, int h, double sigma, int radius, double* dog) {
+    std::vector<double> g(2 * radius + 1), tmp((size_t)w * h);
+    or_gauss_taps(sigma, radius, g.data());
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            double acc = 0.0;
+            for (int i = -radius; i <= radius; ++i)
+                acc = acc + g[i + radius] * (double)img[(size_t)y * w + clampi(x + i, 0, w - 1)];
+            tmp[(size_t)y * w + x] = acc;
+        }
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            double acc = 0.0;
+            for (int j = -radius; j <= radius; ++j)
+                acc = acc + g[j + radius] * tmp[(size_t)clampi(y + j, 0, h - 1) * w + x];
+            dog[(size_t)y * w + x] = (double)img[(size_t)y * w + x] - acc;
+        }
+}
+
+void or_dog_mask(const uint8_t* img, int w, int h, double sigma, int radius, double thresh, int min_on,
+                 int min_off, uint8_t* mask) {
+    std::vector<double> dog((size_t)w * h);
+    or_dog(img, w, h, sigma, radius, dog.data());
+    std::vector<uint8_t> m((size_t)w * h);
+    for (size_t i = 0; i < m.size(); ++i) m[i] = std::fabs(dog[i]) > thresh ? 1 : 0;
+    speckle(m, w, h, 1, min_on);
+    std::vector<uint8_t> d((size_t)w * h, 0);
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            uint8_t v = 0;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int xx = x + dx, yy = y + dy;
+                    if (xx >= 0 && xx < w && yy >= 0 && yy < h && m[(size_t)yy * w + xx]) v = 1;
+                }
+            d[(size_t)y * w + x] = v;
+        }
+    speckle(d, w, h, 0, min_off);
+    std::memcpy(mask, d.data(), d.size());
+}
+
+// Components of the value v with fewer than min_size pixels flip (the
+// speckle step alone, for the pins).
+void or_speckle(uint8_t* m, int w, int h, int v, int min_size) {
+    std::vector<uint8_t> t(m, m + (size_t)w * h);
+    speckle(t, w, h, (uint8_t)v, min_size);
+    std::memcpy(m, t.data(), t.size());
+}
+
+// ---------------------------------------------------------------------------
+// Geometric consistency by mutual reprojection (Alg. 4): for each pixel p of
+// the reference map with depth d > 0 and each neighbouring map k, the point
+// X = d K^-1 p~ goes to view k (X_k = R_k X + t_k, R_k|t_k reference to view
+// k), is projected to the continuous point p_k, takes the depth d_k of the
+// pixel containing p_k (a miss outside the image, behind a camera or where
+// d_k = 0), is lifted with d_k K^-1 p_k~ and mapped back to the reference,
+// where its projection p' gives the reprojection error ||p - p'||.  hits
+// counts the maps with error < eta_r; keep = hits >= eta_h.  Double
+// precision; pixel centres at (x + 0.5, y + 0.5).
+// ---------------------------------------------------------------------------
+void or_geo_consistency(int w, int h, const double* K, const float* depth_ref, int n_nb,
+                        const float* const* depth_nb, const double* R, const double* t, double eta_r, int eta_h,
+                        int32_t* hits, uint8_t* keep) {
+    double Ki[9], Kl[9];
+    or_kinv_level(K, 0, Ki, Kl);
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            const size_t p = (size_t)y * w + x;
+            const double d = depth_ref[p];
+            int nh = 0;
+            if (d > 0.0) {
+                const double u0 = x + 0.5, v0 = y + 0.5;
+                double ray[3];
+                ray_of(Ki, u0, v0, ray);
+                const double X[3] = {d * ray[0], d * ray[1], d * ray[2]};
+                for (int k = 0; k < n_nb; ++k) {
+                    const double* Rk = R + 9 * k;
+                    const double* tk = t + 3 * k;
+                    double Xk[3];
+                    for (int i = 0; i < 3; ++i) Xk[i] = Rk[3 * i] * X[0] + Rk[3 * i + 1] * X[1] + Rk[3 * i + 2] * X[2] + tk[i];
+                    if (!(Xk[2] > 0.0)) continue;
+                    const double uk = (K[0] * Xk[0] + K[1] * Xk[1] + K[2] * Xk[2]) / Xk[2];
+                    const double vk = (K[3] * Xk[0] + K[4] * Xk[1] + K[5] * Xk[2]) / Xk[2];
+                    const double fx = std::floor(uk), fy = std::floor(vk);
+                    if (!(fx >= 0.0 && fx < (double)w && fy >= 0.0 && fy < (double)h)) continue;
+                    const double dk = depth_nb[k][(size_t)fy * w + (size_t)fx];
+                    if (!(dk > 0.0)) continue;
+                    double rk[3];
+                    ray_of(Ki, uk, vk, rk);
+                    const double Y[3] = {dk * rk[0] - tk[0], dk * rk[1] - tk[1], dk * rk[2] - tk[2]};
+                    double Xb[3];
+                    for (int i = 0; i < 3; ++i) Xb[i] = Rk[i] * Y[0] + Rk[3 + i] * Y[1] + Rk[6 + i] * Y[2];
+                    if (!(Xb[2] > 0.0)) continue;
+                    const double ub = (K[0] * Xb[0] + K[1] * Xb[1] + K[2] * Xb[2]) / Xb[2];
+                    const double vb = (K[3] * Xb[0] + K[4] * Xb[1] + K[5] * Xb[2]) / Xb[2];
+                    const double eu = ub - u0, ev = vb - v0;
+                    if (std::sqrt(eu * eu + ev * ev) < eta_r) ++nh;
+                }
+            }
+            if (hits) hits[p] = nh;
+            keep[p] = (d > 0.0 && nh >= eta_h) ? 1 : 0;
+        }
+}
+
+}  // extern "C"
