@@ -56,7 +56,7 @@ typedef int32_t fassmvs_status;
 #define FASSMVS_MAX_LEVELS 5
 
 /* Number of per-stage timers reported by fassmvs_stage_times. */
-#define FASSMVS_N_STAGES 12
+#define FASSMVS_N_STAGES 13
 
 typedef struct {
     int32_t n_levels;          /* pyramid height n, 1..5 (pipeline overview) */
@@ -87,6 +87,8 @@ typedef struct {
                                   floor(s^X m / |X|), P1 and fixed P2 scaled by m;
                                   1 negated, truncated and scaled NCC (0..255 per view),
                                   S = min over X of floor(s^X / |X|), penalties unscaled */
+    int32_t dog_filter;        /* 1: apply the DoG texture filter (Alg. 3, see fassmvs_filter_dog)
+                                  to the level-0 maps before they are returned */
 } fassmvs_config;
 
 typedef struct {
@@ -180,6 +182,35 @@ fassmvs_status fassmvs_frame_work(fassmvs_handle *h, double *out, int32_t n);
  * 20 reference census of level 0 ([H][W] uint64), 30+i pyramid image i of
  * the level (0 reference, 1.. views; [H][W] uint8). */
 fassmvs_status fassmvs_level_map(fassmvs_handle *h, int32_t level, int32_t what, void *dst, size_t dst_bytes);
+
+/* ---------------------------------------------------------------------
+ * Post-processing (Sec. on post-processing and depth map filtering).
+ * Synchronous; maps are caller-owned device memory of one W x H frame.
+ * --------------------------------------------------------------------- */
+
+/* DoG texture filter (Alg. 3): the reference image img ([H][W] uint8) is
+ * smoothed with a 7x7 Gaussian (sigma 1.4, replicate border, double), a
+ * pixel is active where |I - I_smooth| > 0.5, activation areas of fewer than
+ * 7 pixels (4-connected) are dropped, the mask is dilated by 3x3 and
+ * deactivation areas of fewer than 21 pixels are filled.  Where the mask is
+ * 0 (weak texture) depth, normal (xyz) and confidence are set to 0; any map
+ * may be NULL.  mask_out (NULL or [H][W] uint8) receives the mask (1 kept). */
+fassmvs_status fassmvs_filter_dog(fassmvs_handle *h, const uint8_t *img, int32_t w, int32_t hgt, float *depth,
+                                  float *normal, float *confidence, uint8_t *mask_out);
+
+/* Geometric consistency by mutual reprojection (Alg. 4) of a reference depth
+ * map against n_nb (1..8) neighbouring depth maps of the same size:
+ * depth_nb[k] device pointers, R_rel / t_rel host arrays (n_nb x 9, n_nb x 3,
+ * row-major) of the relative poses reference -> neighbour (x_k = R x_ref + t),
+ * K the shared intrinsics.  A pixel with depth d > 0 counts a hit for map k
+ * when its point d K^-1 p, seen in k, lands on a pixel with depth d_k > 0
+ * whose point maps back within eta_r pixels of p (misses outside the image
+ * or behind a camera); pixels with fewer than eta_h hits get depth, normal
+ * and confidence 0.  hits_out / keep_out: NULL or [H][W] int32 / uint8. */
+fassmvs_status fassmvs_filter_geometric(fassmvs_handle *h, int32_t w, int32_t hgt, const double K[9], float *depth,
+                                        float *normal, float *confidence, int32_t n_nb, const float *const *depth_nb,
+                                        const double *R_rel, const double *t_rel, double eta_r, int32_t eta_h,
+                                        int32_t *hits_out, uint8_t *keep_out);
 
 /* ---------------------------------------------------------------------
  * Device-memory plumbing for callers without their own HIP allocator

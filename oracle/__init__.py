@@ -468,6 +468,11 @@ def run_frame(wl, keep=False, levels_only=None):
     if 0 in out["levels"]:
         lv = out["levels"][0]
         out["depth"], out["normal"], out["conf"] = lv["depth"], lv["normal"], lv["conf"]
+        if p.get("dog_filter"):
+            keep = dog_mask(pyr_ref[0]).astype(bool)
+            out["depth"] = np.where(keep, out["depth"], 0).astype(np.float32)
+            out["normal"] = np.where(keep[..., None], out["normal"], 0).astype(np.float32)
+            out["conf"] = np.where(keep, out["conf"], 0).astype(np.float32)
     out["pyr_ref"] = pyr_ref
     out["pyr_views"] = pyr_views
     return out

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fassmvs.h")
 OK, PENDING = 0, 1
 EINVAL, EUNSUPPORTED, ENOMEM, EBUSY, EDEVICE, ENOTFOUND = -1, -2, -3, -4, -5, -6
 MEM_HOST, MEM_DEVICE = 0, 1
-N_STAGES = 12
+N_STAGES = 13
 
 
 class FassmvsError(RuntimeError):
@@ -38,7 +38,7 @@ class Config(C.Structure):
         ("normal_radius", C.c_int32), ("normal_beta", C.c_double), ("conf_rho_deg", C.c_double),
         ("device", C.c_int32), ("stream", C.c_void_p), ("hbm_budget_bytes", C.c_uint64),
         ("profile", C.c_int32), ("keep_levels", C.c_int32), ("sgm_debug", C.c_int32),
-        ("cost", C.c_int32),
+        ("cost", C.c_int32), ("dog_filter", C.c_int32),
     ]
 
 
@@ -91,6 +91,8 @@ def _declare(L):
         "fassmvs_stage_warp": (st, [vp, vp, i32, i32, vp, i32, i32, vp]),
         "fassmvs_stage_cost": (st, [vp, i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "fassmvs_stage_cost_ncc": (st, [vp, i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "fassmvs_filter_dog": (st, [vp, vp, i32, i32, vp, vp, vp, vp]),
+        "fassmvs_filter_geometric": (st, [vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, dbl, i32, vp, vp]),
         "fassmvs_stage_sgm": (st, [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]),
         "fassmvs_stage_sgm_pg": (st, [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp,
                                       vp, vp]),
@@ -136,6 +138,7 @@ def config_from_params(params: dict, **kw) -> Config:
         if k in params:
             setattr(c, k, params[k])
     c.cost = {"census": 0, "ncc": 1}[params.get("cost", "census")]
+    c.dog_filter = int(params.get("dog_filter", 0))
     for k, v in kw.items():
         setattr(c, k, v)
     return c
@@ -377,6 +380,28 @@ class Handle:
         self._check(lib().fassmvs_stage_cost_ncc(self.h, w, h, ref_img.vp, len(side), vptr, sd, cw, ch, len(Ga), Gp,
                                                  Wp, Hp, _vp(offs), _vp(warped), out.vp))
         return out
+
+    def filter_dog(self, img: DeviceArray, depth=None, normal=None, conf=None, want_mask=True):
+        """DoG texture filter on device maps (modified in place); returns the mask."""
+        h, w = img.shape
+        mask = self.empty((h, w), np.uint8) if want_mask else None
+        self._check(lib().fassmvs_filter_dog(self.h, img.vp, w, h, _vp(depth), _vp(normal), _vp(conf), _vp(mask)))
+        return mask
+
+    def filter_geometric(self, K, depth: DeviceArray, nb_depths, R_rel, t_rel, eta_r=10.0, eta_h=3, normal=None,
+                         conf=None):
+        """Geometric consistency filter; returns (hits, keep) device arrays."""
+        h, w = depth.shape
+        hits = self.empty((h, w), np.int32)
+        keep = self.empty((h, w), np.uint8)
+        n = len(nb_depths)
+        ptrs = (C.c_void_p * n)(*[d.ptr for d in nb_depths])
+        Ka, Kp = _arr(K, np.float64)
+        Ra, Rp = _arr(R_rel, np.float64)
+        ta, tp = _arr(t_rel, np.float64)
+        self._check(lib().fassmvs_filter_geometric(self.h, w, h, Kp, depth.vp, _vp(normal), _vp(conf), n, ptrs, Rp,
+                                                   tp, float(eta_r), int(eta_h), hits.vp, keep.vp))
+        return hits, keep
 
     def stage_sgm(self, S: DeviceArray, W, p1, lut, ref: DeviceArray, n_paths, offs=None, dI=None,
                   want_lr=False, want_sbar=False, want_wta=True):

@@ -126,4 +126,27 @@ struct SeedArgs {
 };
 hipError_t launch_seed(const SeedArgs &a, hipStream_t s);
 
+// ---------------------------------------------------------------- post filters
+struct PostArgs {
+    int radius;               // Gaussian radius (3 for the 7x7 kernel)
+    double taps[15];          // normalised taps, radius*2+1 used
+    double thresh;            // |DoG| threshold (0..255 scale)
+    int min_on, min_off;      // speckle sizes for activation / deactivation areas
+};
+hipError_t launch_dog_mask(const uint8_t *img, int w, int h, const PostArgs &a, double *tmp, uint8_t *m0, uint8_t *m1,
+                           hipStream_t s);
+hipError_t launch_apply_keep(const uint8_t *keep, size_t n, float *depth, float *normal, float *conf, hipStream_t s);
+
+struct GeoArgs {
+    int w, h;
+    const float *depth_ref;
+    int n_nb;
+    const float *depth_nb[kMaxViews];
+    double R[kMaxViews][9], t[kMaxViews][3];   // reference -> neighbour
+    double K[9], Kinv[9];
+    double eta_r;
+    int eta_h;
+};
+hipError_t launch_geo(const GeoArgs &a, int32_t *hits, uint8_t *keep, hipStream_t s);
+
 }  // namespace fmvs

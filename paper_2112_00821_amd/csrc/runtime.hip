@@ -25,11 +25,11 @@ namespace {
 
 enum Stage {
     ST_UPLOAD = 0, ST_PYR, ST_CENSUS, ST_SWEEP, ST_SGM_DIRS, ST_SGM_WTA, ST_REFINE, ST_MEDIAN,
-    ST_NORMALS, ST_SEED, ST_OUTPUT, ST_SGM_DEBUG, ST_COUNT
+    ST_NORMALS, ST_SEED, ST_OUTPUT, ST_SGM_DEBUG, ST_POST, ST_COUNT
 };
 static_assert(ST_COUNT == FASSMVS_N_STAGES, "stage count");
 const char *kStageNames[ST_COUNT] = {"upload", "pyramid", "census", "sweep", "sgm_dirs", "sgm_wta",
-                                     "refine", "median", "normals", "seed", "output", "sgm_debug"};
+                                     "refine", "median", "normals", "seed", "output", "sgm_debug", "post"};
 
 std::string g_create_error;
 
@@ -103,6 +103,7 @@ struct fassmvs_handle {
     DevBuf ct, S, wta, c3, params, work_ctr;
     DevBuf sgmbuf[8];
     DevBuf sbar;
+    DevBuf post_tmp, post_m0, post_m1, post_hits;
     struct LevelBufs {
         DevBuf depth_raw, depth, nraw, normal, conf, label, fam, offs, dI, dbar, nbar;
     } lb[FASSMVS_MAX_LEVELS];
@@ -291,6 +292,26 @@ void homography(const double *K, const double *Ki, const double *R, const double
         }
 }
 
+// Parameters of the DoG texture filter: 7x7 Gaussian with sigma
+// 0.3 ((7 - 1) / 2 - 1) + 0.8 = 1.4, taps normalised to sum 1, threshold 0.5
+// on the 0..255 scale, speckle sizes 7 (activation) and 21 (deactivation).
+PostArgs dog_args() {
+    PostArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.radius = 3;
+    const double sigma = 1.4;
+    double sum = 0.0;
+    for (int i = -a.radius; i <= a.radius; ++i) {
+        a.taps[i + a.radius] = std::exp(-(double)(i * i) / (2.0 * sigma * sigma));
+        sum += a.taps[i + a.radius];
+    }
+    for (int i = 0; i <= 2 * a.radius; ++i) a.taps[i] /= sum;
+    a.thresh = 0.5;
+    a.min_on = 7;
+    a.min_off = 21;
+    return a;
+}
+
 fassmvs_status validate_config(const fassmvs_config *c, std::string &msg) {
     if (c->n_levels < 1 || c->n_levels > FASSMVS_MAX_LEVELS) { msg = "n_levels must be 1..5"; return FASSMVS_EINVAL; }
     if (!(c->census_w & 1) || !(c->census_h & 1) || c->census_w < 3 || c->census_h < 3) {
@@ -320,6 +341,7 @@ fassmvs_status validate_config(const fassmvs_config *c, std::string &msg) {
         return FASSMVS_EINVAL;
     }
     if (c->window_labels < 0) { msg = "window_labels must be >= 0"; return FASSMVS_EINVAL; }
+    if (c->dog_filter != 0 && c->dog_filter != 1) { msg = "dog_filter must be 0 or 1"; return FASSMVS_EINVAL; }
     if (c->normal_radius < 1 || c->normal_radius > 4) { msg = "normal_radius must be 1..4"; return FASSMVS_EINVAL; }
     if (!(c->normal_beta > 0.0) || !(c->conf_rho_deg > 0.0 && c->conf_rho_deg < 90.0)) {
         msg = "normal_beta > 0 and 0 < rho < 90 required";
@@ -485,6 +507,9 @@ fassmvs_status alloc_frame(fassmvs_handle *h, const FramePlan &P) {
         if ((st = ensure(h, h->sgmbuf[i], NDmax * 2)) != FASSMVS_OK) return st;
     if (c.sgm_debug && (st = ensure(h, h->sbar, NDmax * 2)) != FASSMVS_OK) return st;
     if ((st = ensure(h, h->wta, N0 * 2)) != FASSMVS_OK) return st;
+    if (c.dog_filter && ((st = ensure(h, h->post_tmp, N0 * 8)) || (st = ensure(h, h->post_m0, N0)) ||
+                         (st = ensure(h, h->post_m1, N0))))
+        return st;
     if ((st = ensure(h, h->c3, N0 * 6)) != FASSMVS_OK) return st;
     if ((st = ensure(h, h->params, P.blob.size() * 8)) != FASSMVS_OK) return st;
     if ((st = ensure(h, h->work_ctr, 8)) != FASSMVS_OK) return st;
@@ -708,6 +733,16 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
             a.normal = (float *)B.normal.p;
             a.conf = (float *)B.conf.p;
             HIPCHK(h, launch_normals(a, h->stream), "normals launch");
+        }
+        if (l == 0 && c.dog_filter) {
+            Timer t(h, ST_POST);
+            PostArgs pa = dog_args();
+            HIPCHK(h, launch_dog_mask(ref, L.w, L.h, pa, (double *)h->post_tmp.p, (uint8_t *)h->post_m0.p,
+                                      (uint8_t *)h->post_m1.p, h->stream),
+                   "dog filter");
+            HIPCHK(h, launch_apply_keep((const uint8_t *)h->post_m1.p, N, (float *)B.depth.p, (float *)B.normal.p,
+                                        (float *)B.conf.p, h->stream),
+                   "dog apply");
         }
         if (l > 0) {
             Timer t(h, ST_SEED);
@@ -1218,6 +1253,60 @@ fassmvs_status fassmvs_stage_cost_ncc(fassmvs_handle *h, int32_t w, int32_t hgt,
     fassmvs_status st = stage_cost_any(h, 1, w, hgt, nullptr, ref_img, n_views, views, view_side, cw, ch, n_fam, G,
                                        W, H, offs, warped, S);
     if (st != FASSMVS_OK) return st;
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_filter_dog(fassmvs_handle *h, const uint8_t *img, int32_t w, int32_t hgt, float *depth,
+                                  float *normal, float *confidence, uint8_t *mask_out) {
+    STAGE_BEGIN;
+    if (!img || w < 1 || hgt < 1 || (size_t)w * hgt > ((size_t)1 << 28)) return fail(h, FASSMVS_EINVAL, "bad DoG arguments");
+    const size_t N = (size_t)w * hgt;
+    fassmvs_status st;
+    if ((st = ensure(h, h->post_tmp, N * 8)) || (st = ensure(h, h->post_m0, N)) || (st = ensure(h, h->post_m1, N)))
+        return st;
+    PostArgs pa = dog_args();
+    HIPCHK(h, launch_dog_mask(img, w, hgt, pa, (double *)h->post_tmp.p, (uint8_t *)h->post_m0.p,
+                              (uint8_t *)h->post_m1.p, h->stream),
+           "dog filter");
+    HIPCHK(h, launch_apply_keep((const uint8_t *)h->post_m1.p, N, depth, normal, confidence, h->stream), "dog apply");
+    if (mask_out)
+        HIPCHK(h, hipMemcpyAsync(mask_out, h->post_m1.p, N, hipMemcpyDeviceToDevice, h->stream), "mask copy");
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_filter_geometric(fassmvs_handle *h, int32_t w, int32_t hgt, const double K[9], float *depth,
+                                        float *normal, float *confidence, int32_t n_nb, const float *const *depth_nb,
+                                        const double *R_rel, const double *t_rel, double eta_r, int32_t eta_h,
+                                        int32_t *hits_out, uint8_t *keep_out) {
+    STAGE_BEGIN;
+    if (!K || !depth || w < 1 || hgt < 1 || (size_t)w * hgt > ((size_t)1 << 28) || n_nb < 1 || n_nb > kMaxViews ||
+        !depth_nb || !R_rel || !t_rel || !(eta_r > 0.0) || eta_h < 0)
+        return fail(h, FASSMVS_EINVAL, "bad geometric filter arguments");
+    GeoArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.w = w;
+    a.h = hgt;
+    a.depth_ref = depth;
+    a.n_nb = n_nb;
+    for (int k = 0; k < n_nb; ++k) {
+        if (!depth_nb[k]) return fail(h, FASSMVS_EINVAL, "null neighbour map");
+        if (!finite_all(R_rel + 9 * k, 9) || !finite_all(t_rel + 3 * k, 3)) return fail(h, FASSMVS_EINVAL, "bad pose");
+        a.depth_nb[k] = depth_nb[k];
+        std::memcpy(a.R[k], R_rel + 9 * k, sizeof(a.R[k]));
+        std::memcpy(a.t[k], t_rel + 3 * k, sizeof(a.t[k]));
+    }
+    double Kl[9];
+    if (!kinv_level(K, 0, Kl, a.Kinv)) return fail(h, FASSMVS_EINVAL, "K must have positive focal lengths");
+    std::memcpy(a.K, K, sizeof(a.K));
+    a.eta_r = eta_r;
+    a.eta_h = eta_h;
+    const size_t N = (size_t)w * hgt;
+    fassmvs_status st;
+    if ((st = ensure(h, h->post_m0, N))) return st;
+    uint8_t *keep = (uint8_t *)h->post_m0.p;
+    HIPCHK(h, launch_geo(a, hits_out, keep, h->stream), "geometric filter");
+    HIPCHK(h, launch_apply_keep(keep, N, depth, normal, confidence, h->stream), "geometric apply");
+    if (keep_out) HIPCHK(h, hipMemcpyAsync(keep_out, keep, N, hipMemcpyDeviceToDevice, h->stream), "keep copy");
     STAGE_END;
 }
 
