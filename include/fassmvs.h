@@ -104,7 +104,10 @@ typedef struct {
     double delta_min;          /* nearest plane distance, > 0 */
     double delta_max;          /* farthest plane distance, > delta_min */
     int32_t count;             /* planes at the coarsest level (2..256); level l uses
-                                  count * 2^(n-1-l) planes uniform in 1/delta */
+                                  count * 2^(n-1-l) planes uniform in 1/delta.  0: as many
+                                  as the cross-ratio construction yields at the coarsest
+                                  level for the view with the longest epipolar segment
+                                  (fassmvs_cross_ratio_planes), capped at 256 */
 } fassmvs_plane_family;
 
 /* Paper defaults: 8 paths, SGM^Pi, census 9x7, P1 24 (census 9x7 setting of
@@ -182,6 +185,35 @@ fassmvs_status fassmvs_frame_work(fassmvs_handle *h, double *out, int32_t n);
  * 20 reference census of level 0 ([H][W] uint64), 30+i pyramid image i of
  * the level (0 reference, 1.. views; [H][W] uint8). */
 fassmvs_status fassmvs_level_map(fassmvs_handle *h, int32_t level, int32_t what, void *dst, size_t dst_bytes);
+
+/* ---------------------------------------------------------------------
+ * Plane set (host only, no handle): bounding planes and the cross-ratio
+ * sampling steps.
+ * --------------------------------------------------------------------- */
+
+/* Bounding plane distances for plane normal n (unit, facing the camera) and
+ * the depth range [d_min, d_max] (Sec. on bounding planes): the reference
+ * frustum's corner rays through the image corners (0,0), (w,0), (0,h), (w,h)
+ * meet the near plane z = d_min and the far plane z = d_max; out[0] = the
+ * least |n^T X| over the near corners, out[1] = the largest over the far
+ * corners.  EINVAL on bad input. */
+fassmvs_status fassmvs_bounding_planes(const double K[9], int32_t w, int32_t hgt, const double n[3], double d_min,
+                                       double d_max, double out[2]);
+
+/* Plane distances whose images move by one pixel (Alg. 2, cross-ratio):
+ * for the image corner (pixel centre) whose images in view k on the two
+ * bounding planes lie farthest apart, points stepped one pixel apart along
+ * that epipolar segment are mapped to plane distances through the
+ * cross-ratio of the view-k rays to the epipole, the two segment ends and
+ * the point.  R, t: reference -> view k (x_k = R x_ref + t).  The list runs
+ * from delta_max down to delta_min (appended when the segment is not a
+ * whole number of pixels).  *count receives its length; deltas (host,
+ * max_planes entries) is written when it fits, else EUNSUPPORTED.  EINVAL
+ * when the camera centre of view k is not in front of the nearest plane or
+ * no corner ray meets both planes. */
+fassmvs_status fassmvs_cross_ratio_planes(const double K[9], int32_t w, int32_t hgt, const double R[9],
+                                          const double t[3], const double n[3], double delta_min, double delta_max,
+                                          int32_t max_planes, double *deltas, int32_t *count);
 
 /* ---------------------------------------------------------------------
  * Post-processing (Sec. on post-processing and depth map filtering).

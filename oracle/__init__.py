@@ -87,6 +87,8 @@ def _declare(L):
         "or_dog_mask": (None, [vp, i, i, d, i, d, i, i, vp]),
         "or_speckle": (None, [vp, i, i, i, i]),
         "or_geo_consistency": (None, [i, i, vp, vp, i, vp, vp, vp, d, i, vp, vp]),
+        "or_bounding_planes": (i, [vp, i, i, vp, d, d, vp]),
+        "or_cross_ratio_planes": (i, [vp, i, i, vp, vp, vp, d, d, i, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -365,12 +367,31 @@ def delta_i(dbar, nbar, Kinv, fam_n, step):
 # frame driver
 # ---------------------------------------------------------------------------
 
+def family_count(wl, fam):
+    """Planes of a family at the coarsest level; count 0 takes the length of
+    the cross-ratio list (coarsest-level intrinsics) of the view with the
+    longest one, capped at 256."""
+    if int(fam["count"]) != 0:
+        return int(fam["count"])
+    n = wl["params"]["n_levels"]
+    _, Kt = kinv_level(np.asarray(wl["K"], np.float64), n - 1)
+    wt, ht = wl["width"] >> (n - 1), wl["height"] >> (n - 1)
+    best = 0
+    for v in wl["views"]:
+        R, t = relative_pose(wl["ref"]["R"], wl["ref"]["t"], v["R"], v["t"])
+        try:
+            best = max(best, len(cross_ratio_planes(Kt, wt, ht, R, t, fam["n"], fam["delta_min"], fam["delta_max"])))
+        except ValueError:
+            pass
+    return min(best, 256)
+
+
 def level_plan(wl, level):
     """Per-level plane families: plane count, window size, lists, normals."""
     p = wl["params"]
     n = p["n_levels"]
     fams = wl["families"]
-    G = [int(f["count"]) << (n - 1 - level) for f in fams]
+    G = [family_count(wl, f) << (n - 1 - level) for f in fams]
     if level == n - 1 or p["window_labels"] <= 0:
         W = list(G)
     else:
@@ -525,3 +546,28 @@ def geo_consistency(K, depth_ref, depth_nb, R, t, eta_r=10.0, eta_h=3):
                              _p(_c(R, np.float64)), _p(_c(t, np.float64)), float(eta_r), int(eta_h), _p(hits),
                              _p(keep))
     return hits, keep
+
+
+# ----------------------------------------------------------------- plane set
+def bounding_planes(K, w, h, n, d_min, d_max):
+    out = np.zeros(2)
+    r = lib().or_bounding_planes(_p(_c(K, np.float64)), int(w), int(h), _p(_c(n, np.float64)), float(d_min),
+                                 float(d_max), _p(out))
+    if r != 0:
+        raise ValueError("bounding_planes: bad input")
+    return float(out[0]), float(out[1])
+
+
+def cross_ratio_planes(K, w, h, R, t, n, d_min, d_max, max_planes=4096):
+    """Plane distances from delta_max to delta_min with one-pixel image steps
+    (Alg. 2); R, t: reference -> view k."""
+    out = np.zeros(max_planes)
+    cnt = C.c_int(0)
+    r = lib().or_cross_ratio_planes(_p(_c(K, np.float64)), int(w), int(h), _p(_c(R, np.float64)),
+                                    _p(_c(t, np.float64)), _p(_c(n, np.float64)), float(d_min), float(d_max),
+                                    int(max_planes), _p(out), C.byref(cnt))
+    if r == -2:
+        raise OverflowError(f"cross-ratio list needs {cnt.value} planes")
+    if r != 0:
+        raise ValueError("cross_ratio_planes: bad input")
+    return out[:cnt.value].copy()

@@ -1105,3 +1105,131 @@ void or_geo_consistency(int w, int h, const double* K, const float* depth_ref, i
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Plane set (Sec. on bounding planes and on the cross-ratio sampling steps).
+// ---------------------------------------------------------------------------
+namespace {
+double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+double sin_angle(const double* a, const double* b) {
+    const double c[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    return std::sqrt(dot3(c, c)) / (std::sqrt(dot3(a, a)) * std::sqrt(dot3(b, b)));
+}
+}  // namespace
+
+extern "C" {
+
+// Bounding plane distances of a family with normal n for the depth range
+// [d_min, d_max]: the reference frustum's corner rays (image corners
+// (0,0), (w,0), (0,h), (w,h)) meet the near plane z = d_min and the far
+// plane z = d_max; delta_min is the least |n^T X| over the near corners and
+// delta_max the largest over the far corners (the printed second formula
+// repeats the minimum; the maximum keeps the whole far face inside the
+// sweep).  Returns -1 on bad input.
+int or_bounding_planes(const double* K, int w, int h, const double* n, double d_min, double d_max, double* out) {
+    if (!(d_min > 0.0) || !(d_max > d_min) || w < 1 || h < 1) return -1;
+    double Ki[9], Kl[9];
+    or_kinv_level(K, 0, Ki, Kl);
+    const double cu[4] = {0.0, (double)w, 0.0, (double)w};
+    const double cv[4] = {0.0, 0.0, (double)h, (double)h};
+    double lo = 1e300, hi = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        double r[3];
+        ray_of(Ki, cu[i], cv[i], r);
+        const double a = std::fabs(dot3(n, r));
+        lo = std::min(lo, a * d_min);
+        hi = std::max(hi, a * d_max);
+    }
+    out[0] = lo;
+    out[1] = hi;
+    return 0;
+}
+
+// Plane distances by the cross-ratio (Alg. 2): among the four corner pixel
+// centres of the reference image, p is the one whose images in view k on
+// the bounding planes lie farthest apart; its ray meets the bounding planes
+// at P_min and P_max, seen from view k at p_min and p_max on the epipolar
+// line.  Stepping from p_max towards p_min one pixel at a time, the points
+// p_i give the cross-ratio Q of the view-k rays to the epipole, p_min, p_i
+// and p_max (sines of the enclosed angles), and the distance of the plane
+// through the corresponding point of p's ray follows from
+//   delta (d_max - d_min) / (d_max (delta - d_min)) = Q,
+// i.e. delta = Q d_max d_min / (Q d_max - (d_max - d_min)).  The list runs
+// from delta_max to delta_min (appended when the segment length is not a
+// whole number of pixels), consecutive planes moving p's image by one
+// pixel.  R, t map reference to view-k coordinates.  *count receives the
+// length; the list is written when it fits in max_planes (return 0), else
+// -2; -1 on bad input (camera centre of view k not in front of the nearest
+// plane, degenerate segment).
+int or_cross_ratio_planes(const double* K, int w, int h, const double* R, const double* t, const double* n,
+                          double dmin, double dmax, int max_planes, double* out, int* count) {
+    *count = 0;
+    if (!(dmin > 0.0) || !(dmax > dmin) || w < 1 || h < 1) return -1;
+    double Ki[9], Kl[9];
+    or_kinv_level(K, 0, Ki, Kl);
+    // view-k camera centre in reference coordinates: C = -R^T t
+    double C[3];
+    for (int i = 0; i < 3; ++i) C[i] = -(R[i] * t[0] + R[3 + i] * t[1] + R[6 + i] * t[2]);
+    if (!(dot3(n, C) + dmin > 0.0)) return -1;
+    auto to_view = [&](const double* X, double* Y) {
+        for (int i = 0; i < 3; ++i) Y[i] = R[3 * i] * X[0] + R[3 * i + 1] * X[1] + R[3 * i + 2] * X[2] + t[i];
+    };
+    auto project = [&](const double* Y, double* uv) {
+        uv[0] = (K[0] * Y[0] + K[1] * Y[1] + K[2] * Y[2]) / Y[2];
+        uv[1] = (K[3] * Y[0] + K[4] * Y[1] + K[5] * Y[2]) / Y[2];
+    };
+    const double cu[4] = {0.5, w - 0.5, 0.5, w - 0.5};
+    const double cv[4] = {0.5, 0.5, h - 0.5, h - 0.5};
+    double best = -1.0, Ymin[3] = {0, 0, 0}, Ymax[3] = {0, 0, 0}, pmin[2] = {0, 0}, pmax[2] = {0, 0};
+    for (int c = 0; c < 4; ++c) {
+        double r[3];
+        ray_of(Ki, cu[c], cv[c], r);
+        const double nr = dot3(n, r);
+        if (!(nr < 0.0)) continue;   // the corner ray does not meet the planes in front
+        const double Pmin[3] = {-dmin / nr * r[0], -dmin / nr * r[1], -dmin / nr * r[2]};
+        const double Pmax[3] = {-dmax / nr * r[0], -dmax / nr * r[1], -dmax / nr * r[2]};
+        double Y0[3], Y1[3], a[2], b[2];
+        to_view(Pmin, Y0);
+        to_view(Pmax, Y1);
+        if (!(Y0[2] > 0.0) || !(Y1[2] > 0.0)) continue;
+        project(Y0, a);
+        project(Y1, b);
+        const double L = std::hypot(a[0] - b[0], a[1] - b[1]);
+        if (L > best) {
+            best = L;
+            std::memcpy(Ymin, Y0, sizeof(Y0));
+            std::memcpy(Ymax, Y1, sizeof(Y1));
+            std::memcpy(pmin, a, sizeof(a));
+            std::memcpy(pmax, b, sizeof(b));
+        }
+    }
+    if (!(best > 0.0)) return -1;
+    const double kx = (pmin[0] - pmax[0]) / best, ky = (pmin[1] - pmax[1]) / best;
+    // rays of view k (camera coordinates): to the epipole (the reference
+    // camera centre, at t), to P_min and to P_max
+    const double* Ve = t;
+    const double s_mm = sin_angle(Ymin, Ymax), s_ex = sin_angle(Ve, Ymax);
+    const int steps = (int)std::floor(best);
+    const bool tail = (double)steps < best;
+    const int total = steps + 1 + (tail ? 1 : 0);
+    *count = total;
+    if (total > max_planes) return -2;
+    int j = 0;
+    for (int i = 0; i <= steps; ++i) {
+        if (i == 0) {
+            out[j++] = dmax;
+            continue;
+        }
+        const double u = pmax[0] + i * kx, v = pmax[1] + i * ky;
+        double Vi[3];
+        ray_of(Ki, u, v, Vi);
+        const double sin_mi = sin_angle(Ymin, Vi);
+        if (!(sin_mi > 0.0)) { out[j++] = dmin; continue; }
+        const double Q = sin_angle(Ve, Vi) * s_mm / (s_ex * sin_mi);
+        out[j++] = Q * dmax * dmin / (Q * dmax - (dmax - dmin));
+    }
+    if (tail) out[j++] = dmin;
+    return 0;
+}
+
+}  // extern "C"

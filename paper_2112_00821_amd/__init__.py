@@ -92,6 +92,8 @@ def _declare(L):
         "fassmvs_stage_cost": (st, [vp, i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "fassmvs_stage_cost_ncc": (st, [vp, i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "fassmvs_filter_dog": (st, [vp, vp, i32, i32, vp, vp, vp, vp]),
+        "fassmvs_bounding_planes": (st, [vp, i32, i32, vp, dbl, dbl, vp]),
+        "fassmvs_cross_ratio_planes": (st, [vp, i32, i32, vp, vp, vp, dbl, dbl, i32, vp, vp]),
         "fassmvs_filter_geometric": (st, [vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, dbl, i32, vp, vp]),
         "fassmvs_stage_sgm": (st, [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]),
         "fassmvs_stage_sgm_pg": (st, [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp,
@@ -142,6 +144,32 @@ def config_from_params(params: dict, **kw) -> Config:
     for k, v in kw.items():
         setattr(c, k, v)
     return c
+
+
+def bounding_planes(K, w, h, n, d_min, d_max):
+    """(delta_min, delta_max) of the family with normal n for the depth range."""
+    Ka, Kp = _arr(K, np.float64)
+    na, npp = _arr(n, np.float64)
+    out = np.zeros(2)
+    st = lib().fassmvs_bounding_planes(Kp, int(w), int(h), npp, float(d_min), float(d_max), out.ctypes.data)
+    if st != OK:
+        raise FassmvsError(st, "bounding planes: bad input")
+    return float(out[0]), float(out[1])
+
+
+def cross_ratio_planes(K, w, h, R, t, n, delta_min, delta_max, max_planes=4096):
+    """Plane distances with one-pixel image steps (delta_max first)."""
+    Ka, Kp = _arr(K, np.float64)
+    Ra, Rp = _arr(R, np.float64)
+    ta, tp = _arr(t, np.float64)
+    na, npp = _arr(n, np.float64)
+    out = np.zeros(max(max_planes, 1))
+    cnt = C.c_int32(0)
+    st = lib().fassmvs_cross_ratio_planes(Kp, int(w), int(h), Rp, tp, npp, float(delta_min), float(delta_max),
+                                          int(max_planes), out.ctypes.data, C.byref(cnt))
+    if st != OK:
+        raise FassmvsError(st, f"cross-ratio planes: status {st}, {cnt.value} planes")
+    return out[:cnt.value].copy()
 
 
 class DeviceArray:

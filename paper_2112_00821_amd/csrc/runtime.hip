@@ -312,6 +312,74 @@ PostArgs dog_args() {
     return a;
 }
 
+// Cross-ratio plane list (Alg. 2).  Writes up to cap distances into out
+// and returns the list length, or -1 on degenerate geometry.
+int cross_ratio_list(const double *K, int w, int h, const double *R, const double *t, const double *n, double dmin,
+                     double dmax, int cap, double *out) {
+    double Kl[9], Ki[9];
+    if (!kinv_level(K, 0, Kl, Ki)) return -1;
+    double Ck[3];   // camera centre of view k in reference coordinates
+    for (int i = 0; i < 3; ++i) Ck[i] = -(R[0 * 3 + i] * t[0] + R[1 * 3 + i] * t[1] + R[2 * 3 + i] * t[2]);
+    if (!(n[0] * Ck[0] + n[1] * Ck[1] + n[2] * Ck[2] + dmin > 0.0)) return -1;
+    auto cross_norm = [](const double *a, const double *b) {
+        const double c0 = a[1] * b[2] - a[2] * b[1], c1 = a[2] * b[0] - a[0] * b[2], c2 = a[0] * b[1] - a[1] * b[0];
+        return std::sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    };
+    auto norm = [](const double *a) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); };
+    auto sin_between = [&](const double *a, const double *b) { return cross_norm(a, b) / (norm(a) * norm(b)); };
+    double seg = -1.0, q0[3] = {0, 0, 0}, q1[3] = {0, 0, 0}, i0[2] = {0, 0}, i1[2] = {0, 0};
+    for (int c = 0; c < 4; ++c) {
+        const double u = (c & 1) ? w - 0.5 : 0.5, v = (c & 2) ? h - 0.5 : 0.5;
+        const double r[3] = {Ki[0] * u + Ki[1] * v + Ki[2], Ki[3] * u + Ki[4] * v + Ki[5], Ki[6] * u + Ki[7] * v + Ki[8]};
+        const double nr = n[0] * r[0] + n[1] * r[1] + n[2] * r[2];
+        if (!(nr < 0.0)) continue;
+        double ends[2][3], img[2][2];
+        bool ok = true;
+        for (int e = 0; e < 2; ++e) {
+            const double s = -(e == 0 ? dmin : dmax) / nr;
+            const double X[3] = {s * r[0], s * r[1], s * r[2]};
+            for (int i = 0; i < 3; ++i) ends[e][i] = R[3 * i] * X[0] + R[3 * i + 1] * X[1] + R[3 * i + 2] * X[2] + t[i];
+            if (!(ends[e][2] > 0.0)) { ok = false; break; }
+            img[e][0] = (K[0] * ends[e][0] + K[1] * ends[e][1] + K[2] * ends[e][2]) / ends[e][2];
+            img[e][1] = (K[3] * ends[e][0] + K[4] * ends[e][1] + K[5] * ends[e][2]) / ends[e][2];
+        }
+        if (!ok) continue;
+        const double L = std::hypot(img[0][0] - img[1][0], img[0][1] - img[1][1]);
+        if (L > seg) {
+            seg = L;
+            std::memcpy(q0, ends[0], sizeof(q0));
+            std::memcpy(q1, ends[1], sizeof(q1));
+            std::memcpy(i0, img[0], sizeof(i0));
+            std::memcpy(i1, img[1], sizeof(i1));
+        }
+    }
+    if (!(seg > 0.0)) return -1;
+    const int whole = (int)std::floor(seg);
+    const int len = whole + 1 + ((double)whole < seg ? 1 : 0);
+    const double dx = (i0[0] - i1[0]) / seg, dy = (i0[1] - i1[1]) / seg;
+    const double s01 = sin_between(q0, q1), se1 = sin_between(t, q1);
+    for (int i = 0; i < len && i < cap; ++i) {
+        double d;
+        if (i == 0) {
+            d = dmax;
+        } else if (i > whole) {
+            d = dmin;
+        } else {
+            const double u = i1[0] + i * dx, v = i1[1] + i * dy;
+            const double V[3] = {Ki[0] * u + Ki[1] * v + Ki[2], Ki[3] * u + Ki[4] * v + Ki[5], Ki[6] * u + Ki[7] * v + Ki[8]};
+            const double s0i = sin_between(q0, V);
+            if (!(s0i > 0.0)) {
+                d = dmin;
+            } else {
+                const double Q = sin_between(t, V) * s01 / (se1 * s0i);
+                d = Q * dmax * dmin / (Q * dmax - (dmax - dmin));
+            }
+        }
+        out[i] = d;
+    }
+    return len;
+}
+
 fassmvs_status validate_config(const fassmvs_config *c, std::string &msg) {
     if (c->n_levels < 1 || c->n_levels > FASSMVS_MAX_LEVELS) { msg = "n_levels must be 1..5"; return FASSMVS_EINVAL; }
     if (!(c->census_w & 1) || !(c->census_h & 1) || c->census_w < 3 || c->census_h < 3) {
@@ -398,8 +466,8 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
             return fail(h, FASSMVS_EINVAL, "plane normals must be unit vectors facing the camera");
         if (!(pf.delta_min > 0.0) || !(pf.delta_max > pf.delta_min) || !std::isfinite(pf.delta_max))
             return fail(h, FASSMVS_EINVAL, "plane distances need 0 < delta_min < delta_max");
-        if (pf.count < 2 || pf.count > FASSMVS_MAX_TOP_PLANES)
-            return fail(h, FASSMVS_EINVAL, "plane count at the coarsest level must be 2..256");
+        if (pf.count != 0 && (pf.count < 2 || pf.count > FASSMVS_MAX_TOP_PLANES))
+            return fail(h, FASSMVS_EINVAL, "plane count at the coarsest level must be 0 or 2..256");
         for (int i = 0; i < 3; ++i) P.fam_n[f][i] = pf.n[i];
         // every camera centre in front of the nearest plane
         for (int k = 0; k < n_views; ++k) {
@@ -408,6 +476,27 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
                 C[i] = -(Rrel[k][0 * 3 + i] * trel[k][0] + Rrel[k][1 * 3 + i] * trel[k][1] + Rrel[k][2 * 3 + i] * trel[k][2]);
             if (!(pf.n[0] * C[0] + pf.n[1] * C[1] + pf.n[2] * C[2] + pf.delta_min > 0.0))
                 return fail(h, FASSMVS_EINVAL, "a camera centre lies behind the nearest sweep plane");
+        }
+    }
+    // coarsest-level plane counts; count 0 takes the cross-ratio list's
+    // length for the view with the longest epipolar segment
+    int fam_count[kMaxFam];
+    {
+        double Kt[9], Kti[9];
+        if (!kinv_level(K, c.n_levels - 1, Kt, Kti)) return fail(h, FASSMVS_EINVAL, "K must have positive focal lengths");
+        const int wt = w >> (c.n_levels - 1), ht = hh >> (c.n_levels - 1);
+        for (int f = 0; f < F; ++f) {
+            fam_count[f] = fam[f].count;
+            if (fam_count[f] != 0) continue;
+            int best = 0;
+            for (int k = 0; k < n_views; ++k) {
+                double tmp[1];
+                const int len = cross_ratio_list(Kt, wt, ht, Rrel[k], trel[k], fam[f].n, fam[f].delta_min,
+                                                 fam[f].delta_max, 1, tmp);
+                best = std::max(best, len);
+            }
+            if (best < 2) return fail(h, FASSMVS_EINVAL, "no cross-ratio plane list for a family with count 0");
+            fam_count[f] = std::min(best, (int)FASSMVS_MAX_TOP_PLANES);
         }
     }
     // penalties: P1 and P2 scaled like the cost
@@ -435,7 +524,7 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
         L.sn = !top && c.sgm_variant == 1;
         int D = 0, sumG = 0;
         for (int f = 0; f < F; ++f) {
-            long G = (long)fam[f].count << (c.n_levels - 1 - l);
+            long G = (long)fam_count[f] << (c.n_levels - 1 - l);
             if (G > 65535) return fail(h, FASSMVS_EUNSUPPORTED, "plane list too long");
             L.G[f] = (int)G;
             L.W[f] = L.windows ? std::min(c.window_labels, L.G[f]) : L.G[f];
@@ -788,6 +877,40 @@ fassmvs_status copy_out(fassmvs_handle *h, void *dst, const void *src, size_t by
 // =================================================================== C ABI
 
 extern "C" {
+
+fassmvs_status fassmvs_bounding_planes(const double K[9], int32_t w, int32_t hgt, const double n[3], double d_min,
+                                       double d_max, double out[2]) {
+    if (!K || !n || !out || w < 1 || hgt < 1 || !(d_min > 0.0) || !(d_max > d_min) || !finite_all(K, 9) ||
+        !finite_all(n, 3))
+        return FASSMVS_EINVAL;
+    double Kl[9], Ki[9];
+    if (!kinv_level(K, 0, Kl, Ki)) return FASSMVS_EINVAL;
+    double lo = 0.0, hi = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        const double u = (c & 1) ? (double)w : 0.0, v = (c & 2) ? (double)hgt : 0.0;
+        const double r[3] = {Ki[0] * u + Ki[1] * v + Ki[2], Ki[3] * u + Ki[4] * v + Ki[5], Ki[6] * u + Ki[7] * v + Ki[8]};
+        const double a = std::fabs(n[0] * r[0] + n[1] * r[1] + n[2] * r[2]);
+        lo = c == 0 ? a * d_min : std::min(lo, a * d_min);
+        hi = c == 0 ? a * d_max : std::max(hi, a * d_max);
+    }
+    out[0] = lo;
+    out[1] = hi;
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_cross_ratio_planes(const double K[9], int32_t w, int32_t hgt, const double R[9],
+                                          const double t[3], const double n[3], double delta_min, double delta_max,
+                                          int32_t max_planes, double *deltas, int32_t *count) {
+    if (count) *count = 0;
+    if (!K || !R || !t || !n || !count || w < 1 || hgt < 1 || !(delta_min > 0.0) || !(delta_max > delta_min) ||
+        max_planes < 0 || (max_planes > 0 && !deltas) || !finite_all(K, 9) || !finite_all(R, 9) || !finite_all(t, 3) ||
+        !finite_all(n, 3))
+        return FASSMVS_EINVAL;
+    const int len = cross_ratio_list(K, w, hgt, R, t, n, delta_min, delta_max, max_planes, deltas);
+    if (len < 0) return FASSMVS_EINVAL;
+    *count = len;
+    return len > max_planes ? FASSMVS_EUNSUPPORTED : FASSMVS_OK;
+}
 
 void fassmvs_config_default(fassmvs_config *c) {
     if (!c) return;

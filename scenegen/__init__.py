@@ -553,7 +553,16 @@ WORKLOADS = {
     "config1_ncc": lambda: with_ncc(config1(0), p2_fixed=400),
     "config2_small_ncc": lambda: with_ncc(config2(1, 320, 184, planes=32, window=32)),
     "config2_ncc": lambda: with_ncc(config2(1)),
+    # plane counts from the cross-ratio construction (count 0)
+    "config1_xr": lambda: with_cross_ratio_counts(config1(0)),
+    "config2_small_xr": lambda: with_cross_ratio_counts(config2(1, 320, 184, planes=32, window=32)),
 }
+
+
+def with_cross_ratio_counts(wl):
+    """The same bundle with every family's coarsest plane count left to the
+    cross-ratio construction (count 0)."""
+    return dict(wl, families=[dict(f, count=0) for f in wl["families"]])
 
 
 def with_ncc(wl, window: int = 5, p1: int = 100, p2_fixed: int | None = None):

@@ -43,7 +43,7 @@ def _compare(orc_out, h, wl, levels):
 
 
 @pytest.mark.parametrize("name", ["config1", "nadir_planar", "config2_small", "config2_ragged", "config3_small",
-                                  "config1_ncc", "config2_small_ncc"])
+                                  "config1_ncc", "config2_small_ncc", "config1_xr", "config2_small_xr"])
 def test_frame_matches_oracle(orc, fm, name):
     wl = scenegen.make_workload(name)
     ref = orc.run_frame(wl, keep=True)
