@@ -245,6 +245,77 @@ fassmvs_status fassmvs_filter_geometric(fassmvs_handle *h, int32_t w, int32_t hg
                                         int32_t *hits_out, uint8_t *keep_out);
 
 /* ---------------------------------------------------------------------
+ * Served form (online mapping from several UAV streams).
+ *
+ * Frames of several streams are submitted as they arrive; each is matched
+ * against its stream's previous keyframes (up to max_keyframes, all before
+ * it in the sequence: a one-sided bundle, m = number of keyframes; a frame
+ * becomes a keyframe when its camera centre moved at least min_baseline
+ * since the last keyframe, the first frame always does), so the stream's
+ * keyframe images stay on the device.  A worker thread admits queued frames
+ * in arrival order into n_slots pipeline slots (each a handle with its own
+ * HIP stream, so admitted frames run concurrently) while the sum of the
+ * admitted frames' footprints (fassmvs_frame_footprint) stays within the
+ * budget, and collects finished frames into result maps on the device.
+ * Results are the same as the plain pipeline's on the same bundle.
+ * --------------------------------------------------------------------- */
+typedef struct fassmvs_server fassmvs_server;
+
+typedef struct {
+    uint64_t request_id;
+    int32_t stream_id;
+    int32_t status;            /* OK, ENOTFOUND (no keyframe to match against yet), or the frame's error */
+    int32_t width, height;
+    int32_t keyframe;          /* 1 if the frame became a keyframe */
+    int32_t n_views;           /* keyframes it was matched against */
+    double latency_ms;         /* submit call to maps ready on the device */
+} fassmvs_server_result;
+
+/* Device bytes one frame holds while it runs (cost volume, path-cost
+ * buffers, pyramids, per-level maps); families with count 0 are counted
+ * at the 256-plane cap. */
+fassmvs_status fassmvs_frame_footprint(const fassmvs_config *cfg, int32_t w, int32_t hgt, int32_t n_views,
+                                       const fassmvs_plane_family *families, int32_t n_families, uint64_t *bytes);
+
+/* Create a server with n_slots (1..16) concurrent pipeline slots, all with
+ * cfg (cfg->stream is ignored: every slot creates its own).  hbm_budget_bytes
+ * 0: 80 % of the device memory free at creation. */
+fassmvs_status fassmvs_server_create(const fassmvs_config *cfg, int32_t n_slots, uint64_t hbm_budget_bytes,
+                                     fassmvs_server **out);
+
+/* Open a stream of width x height frames with intrinsics K and plane
+ * families; *stream_id receives its id. */
+fassmvs_status fassmvs_server_open_stream(fassmvs_server *s, const double K[9], int32_t width, int32_t height,
+                                          const fassmvs_plane_family *families, int32_t n_families,
+                                          int32_t max_keyframes, double min_baseline, int32_t *stream_id);
+
+/* Submit the next frame of a stream (host pixels, copied to the device before
+ * return; pose x_cam = R x_world + t).  The arrival time for the latency is
+ * the moment of the call.  ENOMEM if the frame's footprint exceeds the whole
+ * budget. */
+fassmvs_status fassmvs_server_submit(fassmvs_server *s, int32_t stream_id, const uint8_t *pixels, int32_t stride,
+                                     const double R[9], const double t[3], uint64_t *request_id);
+
+/* Next finished request in completion order: wait_ms 0 non-blocking, -1
+ * blocking, else a bound; PENDING if none.  Its maps (status OK) stay on
+ * the device until fetched. */
+fassmvs_status fassmvs_server_next(fassmvs_server *s, int32_t wait_ms, fassmvs_server_result *out);
+
+/* Copy a finished request's maps (depth W*H, normal W*H*3, confidence W*H
+ * floats; any NULL) to host or device memory and release them; ENOTFOUND
+ * if the request has no maps or was fetched already. */
+fassmvs_status fassmvs_server_fetch(fassmvs_server *s, uint64_t request_id, float *depth, float *normal,
+                                    float *confidence, int32_t mem_kind);
+
+/* Stop taking frames of a stream and drop its keyframes. */
+fassmvs_status fassmvs_server_close_stream(fassmvs_server *s, int32_t stream_id);
+
+const char *fassmvs_server_last_error(const fassmvs_server *s);
+
+/* Finish every queued and running frame, then release everything. */
+void fassmvs_server_destroy(fassmvs_server *s);
+
+/* ---------------------------------------------------------------------
  * Device-memory plumbing for callers without their own HIP allocator
  * (tests, benchmark).  All run on the handle's device and stream.
  * --------------------------------------------------------------------- */

@@ -47,6 +47,11 @@ class Image(C.Structure):
                 ("stride", C.c_int32), ("R", C.c_double * 9), ("t", C.c_double * 3)]
 
 
+class ServerResult(C.Structure):
+    _fields_ = [("request_id", C.c_uint64), ("stream_id", C.c_int32), ("status", C.c_int32), ("width", C.c_int32),
+                ("height", C.c_int32), ("keyframe", C.c_int32), ("n_views", C.c_int32), ("latency_ms", C.c_double)]
+
+
 class PlaneFamily(C.Structure):
     _fields_ = [("n", C.c_double * 3), ("delta_min", C.c_double), ("delta_max", C.c_double),
                 ("count", C.c_int32)]
@@ -93,6 +98,15 @@ def _declare(L):
         "fassmvs_stage_cost_ncc": (st, [vp, i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "fassmvs_filter_dog": (st, [vp, vp, i32, i32, vp, vp, vp, vp]),
         "fassmvs_bounding_planes": (st, [vp, i32, i32, vp, dbl, dbl, vp]),
+        "fassmvs_frame_footprint": (st, [vp, i32, i32, i32, vp, i32, vp]),
+        "fassmvs_server_create": (st, [vp, i32, u64, vp]),
+        "fassmvs_server_open_stream": (st, [vp, vp, i32, i32, vp, i32, i32, dbl, vp]),
+        "fassmvs_server_submit": (st, [vp, i32, vp, i32, vp, vp, vp]),
+        "fassmvs_server_next": (st, [vp, i32, vp]),
+        "fassmvs_server_fetch": (st, [vp, u64, vp, vp, vp, i32]),
+        "fassmvs_server_close_stream": (st, [vp, i32]),
+        "fassmvs_server_last_error": (C.c_char_p, [vp]),
+        "fassmvs_server_destroy": (None, [vp]),
         "fassmvs_cross_ratio_planes": (st, [vp, i32, i32, vp, vp, vp, dbl, dbl, i32, vp, vp]),
         "fassmvs_filter_geometric": (st, [vp, i32, i32, vp, vp, vp, vp, i32, vp, vp, vp, dbl, i32, vp, vp]),
         "fassmvs_stage_sgm": (st, [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]),
@@ -170,6 +184,82 @@ def cross_ratio_planes(K, w, h, R, t, n, delta_min, delta_max, max_planes=4096):
     if st != OK:
         raise FassmvsError(st, f"cross-ratio planes: status {st}, {cnt.value} planes")
     return out[:cnt.value].copy()
+
+
+def _families(families):
+    fams = (PlaneFamily * len(families))()
+    for i, f in enumerate(families):
+        fams[i].n[:] = [float(x) for x in f["n"]]
+        fams[i].delta_min = f["delta_min"]
+        fams[i].delta_max = f["delta_max"]
+        fams[i].count = int(f["count"])
+    return fams
+
+
+class Server:
+    """Served form: concurrent pipeline slots over several streams (see the
+    fassmvs_server_* calls of the header)."""
+
+    def __init__(self, cfg=None, n_slots=4, hbm_budget_bytes=0):
+        self.s = C.c_void_p()
+        cfg = cfg if cfg is not None else default_config()
+        st = lib().fassmvs_server_create(C.byref(cfg), int(n_slots), int(hbm_budget_bytes), C.byref(self.s))
+        if st != OK:
+            raise FassmvsError(st, lib().fassmvs_last_error(None).decode())
+        self.streams = {}
+
+    def _check(self, st):
+        if st < 0:
+            raise FassmvsError(st, lib().fassmvs_server_last_error(self.s).decode())
+        return st
+
+    def open_stream(self, K, width, height, families, max_keyframes=4, min_baseline=1.0):
+        sid = C.c_int32()
+        Kc = (C.c_double * 9)(*[float(x) for x in np.asarray(K, np.float64).ravel()])
+        fams = _families(families)
+        self._check(lib().fassmvs_server_open_stream(self.s, Kc, int(width), int(height), fams, len(families),
+                                                     int(max_keyframes), float(min_baseline), C.byref(sid)))
+        self.streams[sid.value] = (int(width), int(height))
+        return sid.value
+
+    def submit(self, stream_id, img, R, t):
+        a = np.ascontiguousarray(img, np.uint8)
+        rid = C.c_uint64()
+        Rc = (C.c_double * 9)(*[float(x) for x in np.asarray(R, np.float64).ravel()])
+        tc = (C.c_double * 3)(*[float(x) for x in np.asarray(t, np.float64).ravel()])
+        self._check(lib().fassmvs_server_submit(self.s, int(stream_id), a.ctypes.data, a.shape[1], Rc, tc,
+                                                C.byref(rid)))
+        return rid.value
+
+    def next(self, wait_ms=-1):
+        r = ServerResult()
+        st = self._check(lib().fassmvs_server_next(self.s, int(wait_ms), C.byref(r)))
+        if st == PENDING:
+            return None
+        return dict(request_id=r.request_id, stream_id=r.stream_id, status=r.status, width=r.width,
+                    height=r.height, keyframe=r.keyframe, n_views=r.n_views, latency_ms=r.latency_ms)
+
+    def fetch(self, request_id, w, h):
+        depth = np.zeros((h, w), np.float32)
+        normal = np.zeros((h, w, 3), np.float32)
+        conf = np.zeros((h, w), np.float32)
+        self._check(lib().fassmvs_server_fetch(self.s, int(request_id), depth.ctypes.data, normal.ctypes.data,
+                                               conf.ctypes.data, MEM_HOST))
+        return dict(depth=depth, normal=normal, conf=conf)
+
+    def close_stream(self, stream_id):
+        self._check(lib().fassmvs_server_close_stream(self.s, int(stream_id)))
+
+    def close(self):
+        if self.s:
+            lib().fassmvs_server_destroy(self.s)
+            self.s = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 class DeviceArray:

@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfassmvs.so")
-SOURCES = ["k_image.hip", "k_sweep.hip", "k_sgm.hip", "k_post.hip", "runtime.hip"]
+SOURCES = ["k_image.hip", "k_sweep.hip", "k_sgm.hip", "k_post.hip", "runtime.hip", "server.hip"]
 ARCH = os.environ.get("FASSMVS_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

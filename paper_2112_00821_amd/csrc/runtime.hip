@@ -878,6 +878,40 @@ fassmvs_status copy_out(fassmvs_handle *h, void *dst, const void *src, size_t by
 
 extern "C" {
 
+fassmvs_status fassmvs_frame_footprint(const fassmvs_config *cfg, int32_t w, int32_t hgt, int32_t n_views,
+                                       const fassmvs_plane_family *families, int32_t n_families, uint64_t *bytes) {
+    if (!cfg || !families || !bytes || w < 1 || hgt < 1 || n_views < 1 || n_views > kMaxViews || n_families < 1 ||
+        n_families > kMaxFam || cfg->n_levels < 1 || cfg->n_levels > FASSMVS_MAX_LEVELS)
+        return FASSMVS_EINVAL;
+    size_t NDmax = 0, maps = 0;
+    int lw = w, lh = hgt;
+    for (int l = 0; l < cfg->n_levels; ++l) {
+        if (l > 0) {
+            lw /= 2;
+            lh /= 2;
+        }
+        size_t D = 0;
+        for (int f = 0; f < n_families; ++f) {
+            const size_t count = families[f].count > 0 ? (size_t)families[f].count : (size_t)FASSMVS_MAX_TOP_PLANES;
+            const size_t G = count << (cfg->n_levels - 1 - l);
+            const bool windows = l < cfg->n_levels - 1 && cfg->window_labels > 0;
+            D += windows ? std::min((size_t)cfg->window_labels, G) : G;
+        }
+        const size_t N = (size_t)lw * lh;
+        NDmax = std::max(NDmax, N * D);
+        // depth, raw depth, normals (raw, smoothed), confidence, label,
+        // family, offsets and surface-normal offsets per family, seeds
+        maps += N * (4 + 4 + 12 + 12 + 4 + 4 + 4 + 4 * (size_t)n_families + 8 * (size_t)n_families + 4 + 12);
+    }
+    const size_t N0 = (size_t)w * hgt;
+    size_t total = NDmax * (1 + 2 * (size_t)cfg->n_paths) + maps + pyr_total(w, hgt, cfg->n_levels) * (n_views + 1) +
+                   N0 * (8 + 2 + 6);
+    if (cfg->sgm_debug) total += NDmax * 2;
+    if (cfg->dog_filter) total += N0 * 10;
+    *bytes = total;
+    return FASSMVS_OK;
+}
+
 fassmvs_status fassmvs_bounding_planes(const double K[9], int32_t w, int32_t hgt, const double n[3], double d_min,
                                        double d_max, double out[2]) {
     if (!K || !n || !out || w < 1 || hgt < 1 || !(d_min > 0.0) || !(d_max > d_min) || !finite_all(K, 9) ||

@@ -1,0 +1,514 @@
+// Served form of the pipeline: several UAV streams, frames submitted as they
+// arrive, each matched against its stream's previous keyframes (the
+// sliding bundle of the online-mapping use; keyframe when the camera moved
+// at least min_baseline since the last keyframe), admitted into one of
+// n_slots pipeline slots when a slot is free and the frame's device-memory
+// footprint fits the budget, and run concurrently (each slot is a handle
+// with its own HIP stream, so frames overlap on the device).
+//
+// Host code over the library's public C ABI.  A worker thread admits
+// queued frames and collects finished ones; submit and result calls only
+// touch the queues.  Keyframe images stay on the device (per stream, a
+// pool of image buffers with reference counts held by the frames that use
+// them and by the keyframe list).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/fassmvs.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point t0, Clock::time_point t1) {
+    return std::chrono::duration<double, std::milli>(t1 - t0).count();
+}
+
+struct Stream;
+
+// A device copy of one frame's image, returned to its stream's pool when
+// the last user lets go.
+struct DevImage {
+    uint8_t *p = nullptr;
+    Stream *owner = nullptr;
+    ~DevImage();
+};
+
+struct Stream {
+    int id = 0;
+    double K[9];
+    int w = 0, h = 0;
+    std::vector<fassmvs_plane_family> fams;
+    int max_kf = 4;
+    double min_baseline = 1.0;
+    // keyframes, most recent first: image and pose
+    struct Key {
+        std::shared_ptr<DevImage> img;
+        double R[9], t[3], C[3];
+    };
+    std::deque<Key> keys;
+    std::vector<uint8_t *> pool;   // free device image buffers
+    struct Maps {
+        float *depth = nullptr, *normal = nullptr, *conf = nullptr;
+    };
+    std::vector<Maps> map_pool;    // free device result maps
+    std::mutex *pool_mu = nullptr;
+    bool closed = false;
+};
+
+DevImage::~DevImage() {
+    if (p && owner) {
+        std::lock_guard<std::mutex> lk(*owner->pool_mu);
+        owner->pool.push_back(p);
+    }
+}
+
+struct Request {
+    uint64_t id = 0;
+    int stream = 0;
+    Clock::time_point arrival;
+    std::shared_ptr<DevImage> img;
+    double R[9], t[3];
+    std::vector<Stream::Key> views;   // snapshot of the stream's keyframes
+    bool keyframe = false;
+    uint64_t footprint = 0;
+};
+
+struct Result {
+    fassmvs_server_result info;
+    Stream *owner = nullptr;
+    float *depth = nullptr, *normal = nullptr, *conf = nullptr;   // device, from owner's map pool
+};
+
+// Result maps of a stream from its pool (allocated once; hipFree would
+// synchronise the device and stall the frames in flight).
+bool take_maps(Stream &st, Result &r) {
+    {
+        std::lock_guard<std::mutex> lk(*st.pool_mu);
+        if (!st.map_pool.empty()) {
+            Stream::Maps m = st.map_pool.back();
+            st.map_pool.pop_back();
+            r.depth = m.depth;
+            r.normal = m.normal;
+            r.conf = m.conf;
+            r.owner = &st;
+            return true;
+        }
+    }
+    const size_t N = (size_t)st.w * st.h;
+    float *d = nullptr, *n = nullptr, *c = nullptr;
+    if (hipMalloc(&d, N * 4) != hipSuccess || hipMalloc(&n, N * 12) != hipSuccess || hipMalloc(&c, N * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        if (d) hipFree(d);
+        if (n) hipFree(n);
+        if (c) hipFree(c);
+        return false;
+    }
+    r.depth = d;
+    r.normal = n;
+    r.conf = c;
+    r.owner = &st;
+    return true;
+}
+
+void give_maps(Result &r) {
+    if (!r.owner || !r.depth) return;
+    std::lock_guard<std::mutex> lk(*r.owner->pool_mu);
+    r.owner->map_pool.push_back(Stream::Maps{r.depth, r.normal, r.conf});
+    r.depth = r.normal = r.conf = nullptr;
+}
+
+struct Slot {
+    fassmvs_handle *h = nullptr;
+    hipStream_t stream = nullptr;
+    bool busy = false;
+    uint64_t ticket = 0;
+    Request req;
+    Result res;
+};
+
+}  // namespace
+
+struct fassmvs_server {
+    fassmvs_config cfg;
+    uint64_t budget = 0, in_use = 0;
+    std::vector<Slot> slots;
+    std::map<int, std::unique_ptr<Stream>> streams;
+    std::mutex pool_mu;   // image and result-map pools of every stream
+    std::mutex mu;        // queues, streams, results
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> queue;
+    std::deque<Result> done;
+    std::map<uint64_t, Result> fetched_pending;   // results reported but not yet fetched
+    uint64_t next_id = 1;
+    int next_stream = 1;
+    bool stop = false;
+    std::string err;
+    std::thread worker;
+    size_t in_flight = 0;
+};
+
+namespace {
+
+fassmvs_status sfail(fassmvs_server *s, fassmvs_status st, const std::string &m) {
+    if (s) s->err = m;
+    return st;
+}
+
+void camera_centre(const double *R, const double *t, double *C) {
+    for (int i = 0; i < 3; ++i) C[i] = -(R[i] * t[0] + R[3 + i] * t[1] + R[6 + i] * t[2]);
+}
+
+// Admit the head of the queue into free slots while the footprint fits.
+// Called by the worker with s->mu held.
+void admit(fassmvs_server *s) {
+    while (!s->queue.empty()) {
+        Slot *free_slot = nullptr;
+        for (auto &sl : s->slots)
+            if (!sl.busy) {
+                free_slot = &sl;
+                break;
+            }
+        if (!free_slot) return;
+        Request &r = s->queue.front();
+        if (s->in_flight > 0 && s->in_use + r.footprint > s->budget) return;
+        Request req = std::move(r);
+        s->queue.pop_front();
+        Stream &st = *s->streams.at(req.stream);
+        Result res;
+        std::memset(&res.info, 0, sizeof(res.info));
+        res.info.request_id = req.id;
+        res.info.stream_id = req.stream;
+        res.info.width = st.w;
+        res.info.height = st.h;
+        res.info.keyframe = req.keyframe ? 1 : 0;
+        res.info.n_views = (int32_t)req.views.size();
+        if (req.views.empty()) {
+            // nothing to match against yet (first keyframe of a stream)
+            res.info.status = FASSMVS_ENOTFOUND;
+            res.info.latency_ms = ms_since(req.arrival, Clock::now());
+            s->done.push_back(res);
+            s->cv_done.notify_all();
+            continue;
+        }
+        if (!take_maps(st, res)) {
+            res.info.status = FASSMVS_ENOMEM;
+            s->done.push_back(res);
+            s->cv_done.notify_all();
+            continue;
+        }
+        fassmvs_image ref;
+        std::memset(&ref, 0, sizeof(ref));
+        ref.pixels = req.img->p;
+        ref.width = st.w;
+        ref.height = st.h;
+        ref.stride = st.w;
+        std::memcpy(ref.R, req.R, sizeof(ref.R));
+        std::memcpy(ref.t, req.t, sizeof(ref.t));
+        fassmvs_image views[FASSMVS_MAX_VIEWS];
+        int8_t side[FASSMVS_MAX_VIEWS];
+        const int nv = (int)req.views.size();
+        for (int k = 0; k < nv; ++k) {
+            std::memset(&views[k], 0, sizeof(views[k]));
+            views[k].pixels = req.views[k].img->p;
+            views[k].width = st.w;
+            views[k].height = st.h;
+            views[k].stride = st.w;
+            std::memcpy(views[k].R, req.views[k].R, sizeof(views[k].R));
+            std::memcpy(views[k].t, req.views[k].t, sizeof(views[k].t));
+            side[k] = -1;   // earlier in the sequence: one-sided bundle
+        }
+        uint64_t ticket = 0;
+        fassmvs_status rc = fassmvs_submit_frame(free_slot->h, &ref, views, side, nv, st.K, st.fams.data(),
+                                                 (int32_t)st.fams.size(), FASSMVS_MEM_DEVICE, &ticket);
+        if (rc != FASSMVS_OK) {
+            give_maps(res);
+            res.info.status = rc;
+            res.info.latency_ms = ms_since(req.arrival, Clock::now());
+            s->done.push_back(res);
+            s->cv_done.notify_all();
+            continue;
+        }
+        free_slot->busy = true;
+        free_slot->ticket = ticket;
+        free_slot->req = std::move(req);
+        free_slot->res = res;
+        s->in_use += free_slot->req.footprint;
+        s->in_flight++;
+    }
+}
+
+// Collect finished frames (non-blocking).  s->mu held.
+bool collect(fassmvs_server *s) {
+    bool any = false;
+    for (auto &sl : s->slots) {
+        if (!sl.busy) continue;
+        fassmvs_status rc = fassmvs_poll(sl.h, sl.ticket, sl.res.depth, sl.res.normal, sl.res.conf,
+                                         FASSMVS_MEM_DEVICE, 0);
+        if (rc == FASSMVS_PENDING) continue;
+        Result res = sl.res;
+        res.info.status = rc;
+        res.info.latency_ms = ms_since(sl.req.arrival, Clock::now());
+        if (rc != FASSMVS_OK) give_maps(res);
+        s->in_use -= sl.req.footprint;
+        s->in_flight--;
+        sl.busy = false;
+        sl.req = Request();   // drop the image references
+        s->done.push_back(res);
+        any = true;
+    }
+    if (any) s->cv_done.notify_all();
+    return any;
+}
+
+void worker_loop(fassmvs_server *s) {
+    hipSetDevice(s->cfg.device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        if (s->stop && s->queue.empty() && s->in_flight == 0) break;
+        bool progress = collect(s);
+        const size_t before = s->queue.size();
+        admit(s);
+        progress |= s->queue.size() != before;
+        if (!progress) {
+            if (s->in_flight > 0)
+                s->cv_work.wait_for(lk, std::chrono::microseconds(50));
+            else
+                s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+fassmvs_status fassmvs_server_create(const fassmvs_config *cfg, int32_t n_slots, uint64_t hbm_budget_bytes,
+                                     fassmvs_server **out) {
+    if (!out) return FASSMVS_EINVAL;
+    *out = nullptr;
+    if (!cfg || n_slots < 1 || n_slots > 16) return FASSMVS_EINVAL;
+    std::unique_ptr<fassmvs_server> s(new fassmvs_server());
+    s->cfg = *cfg;
+    if (hipSetDevice(cfg->device) != hipSuccess) return FASSMVS_EDEVICE;
+    if (hbm_budget_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return FASSMVS_EDEVICE;
+        hbm_budget_bytes = (uint64_t)(fr * 0.8);
+    }
+    s->budget = hbm_budget_bytes;
+    s->slots.resize(n_slots);
+    for (auto &sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) return FASSMVS_EDEVICE;
+        fassmvs_config c = *cfg;
+        c.stream = sl.stream;
+        c.keep_levels = 0;
+        fassmvs_status st = fassmvs_create(&c, &sl.h);
+        if (st != FASSMVS_OK) {
+            for (auto &o : s->slots) {
+                if (o.h) fassmvs_destroy(o.h);
+                if (o.stream) hipStreamDestroy(o.stream);
+            }
+            return st;
+        }
+    }
+    s->worker = std::thread(worker_loop, s.get());
+    *out = s.release();
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_server_open_stream(fassmvs_server *s, const double K[9], int32_t width, int32_t height,
+                                          const fassmvs_plane_family *families, int32_t n_families,
+                                          int32_t max_keyframes, double min_baseline, int32_t *stream_id) {
+    if (!s || !K || !families || !stream_id || width < 8 || height < 8 || n_families < 1 ||
+        n_families > FASSMVS_MAX_FAMILIES || max_keyframes < 1 || max_keyframes > FASSMVS_MAX_VIEWS ||
+        !(min_baseline >= 0.0))
+        return sfail(s, FASSMVS_EINVAL, "bad stream arguments");
+    std::unique_ptr<Stream> st(new Stream());
+    std::memcpy(st->K, K, sizeof(st->K));
+    st->w = width;
+    st->h = height;
+    st->fams.assign(families, families + n_families);
+    st->max_kf = max_keyframes;
+    st->min_baseline = min_baseline;
+    st->pool_mu = &s->pool_mu;
+    std::lock_guard<std::mutex> lk(s->mu);
+    st->id = s->next_stream++;
+    *stream_id = st->id;
+    s->streams[st->id] = std::move(st);
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_server_submit(fassmvs_server *s, int32_t stream_id, const uint8_t *pixels, int32_t stride,
+                                     const double R[9], const double t[3], uint64_t *request_id) {
+    const Clock::time_point arrival = Clock::now();
+    if (!s || !pixels || !R || !t || !request_id) return sfail(s, FASSMVS_EINVAL, "null argument");
+    Stream *st;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->streams.find(stream_id);
+        if (it == s->streams.end() || it->second->closed) return sfail(s, FASSMVS_ENOTFOUND, "unknown stream");
+        st = it->second.get();
+    }
+    if (stride < st->w) return sfail(s, FASSMVS_EINVAL, "stride smaller than the width");
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(R[i])) return sfail(s, FASSMVS_EINVAL, "non-finite pose");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(t[i])) return sfail(s, FASSMVS_EINVAL, "non-finite pose");
+    // the image goes to the device now: every later frame of the stream that
+    // takes it as a keyframe finds it there
+    uint8_t *dp = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(s->pool_mu);
+        if (!st->pool.empty()) {
+            dp = st->pool.back();
+            st->pool.pop_back();
+        }
+    }
+    if (!dp && hipMalloc(&dp, (size_t)st->w * st->h) != hipSuccess) {
+        (void)hipGetLastError();
+        return sfail(s, FASSMVS_ENOMEM, "image buffer allocation failed");
+    }
+    auto img = std::make_shared<DevImage>();
+    img->p = dp;
+    img->owner = st;
+    if (hipMemcpy2D(dp, st->w, pixels, stride, st->w, st->h, hipMemcpyHostToDevice) != hipSuccess)
+        return sfail(s, FASSMVS_EDEVICE, "image upload failed");
+    Request req;
+    req.arrival = arrival;
+    req.stream = stream_id;
+    req.img = img;
+    std::memcpy(req.R, R, sizeof(req.R));
+    std::memcpy(req.t, t, sizeof(req.t));
+    uint64_t fp = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        req.views.assign(st->keys.begin(), st->keys.end());
+        if (!req.views.empty() &&
+            fassmvs_frame_footprint(&s->cfg, st->w, st->h, (int32_t)req.views.size(), st->fams.data(),
+                                    (int32_t)st->fams.size(), &fp) != FASSMVS_OK)
+            return sfail(s, FASSMVS_EINVAL, "footprint");
+        if (fp > s->budget) return sfail(s, FASSMVS_ENOMEM, "frame footprint exceeds the server's budget");
+        req.id = s->next_id++;
+        double C[3];
+        camera_centre(R, t, C);
+        bool key = st->keys.empty();
+        if (!key) {
+            const double *Cl = st->keys.front().C;
+            const double d = std::sqrt((C[0] - Cl[0]) * (C[0] - Cl[0]) + (C[1] - Cl[1]) * (C[1] - Cl[1]) +
+                                       (C[2] - Cl[2]) * (C[2] - Cl[2]));
+            key = d >= st->min_baseline;
+        }
+        req.keyframe = key;
+        if (key) {
+            Stream::Key k;
+            k.img = img;
+            std::memcpy(k.R, R, sizeof(k.R));
+            std::memcpy(k.t, t, sizeof(k.t));
+            std::memcpy(k.C, C, sizeof(k.C));
+            st->keys.push_front(k);
+            while ((int)st->keys.size() > st->max_kf) st->keys.pop_back();
+        }
+        req.footprint = fp;
+        *request_id = req.id;
+        s->queue.push_back(std::move(req));
+    }
+    s->cv_work.notify_all();
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_server_next(fassmvs_server *s, int32_t wait_ms, fassmvs_server_result *out) {
+    if (!s || !out) return FASSMVS_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto ready = [&] { return !s->done.empty(); };
+    if (!ready()) {
+        if (wait_ms == 0) return FASSMVS_PENDING;
+        if (wait_ms < 0)
+            s->cv_done.wait(lk, ready);
+        else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), ready))
+            return FASSMVS_PENDING;
+    }
+    Result r = s->done.front();
+    s->done.pop_front();
+    *out = r.info;
+    if (r.depth) s->fetched_pending[r.info.request_id] = r;
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_server_fetch(fassmvs_server *s, uint64_t request_id, float *depth, float *normal,
+                                    float *confidence, int32_t mem_kind) {
+    if (!s) return FASSMVS_EINVAL;
+    if (mem_kind != FASSMVS_MEM_HOST && mem_kind != FASSMVS_MEM_DEVICE) return sfail(s, FASSMVS_EINVAL, "bad mem_kind");
+    Result r;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->fetched_pending.find(request_id);
+        if (it == s->fetched_pending.end()) return sfail(s, FASSMVS_ENOTFOUND, "no maps for this request");
+        r = it->second;
+        s->fetched_pending.erase(it);
+    }
+    const size_t N = (size_t)r.info.width * r.info.height;
+    const hipMemcpyKind kind = mem_kind == FASSMVS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    hipError_t e = hipSuccess;
+    if (depth && e == hipSuccess) e = hipMemcpy(depth, r.depth, N * 4, kind);
+    if (normal && e == hipSuccess) e = hipMemcpy(normal, r.normal, N * 12, kind);
+    if (confidence && e == hipSuccess) e = hipMemcpy(confidence, r.conf, N * 4, kind);
+    give_maps(r);
+    return e == hipSuccess ? FASSMVS_OK : sfail(s, FASSMVS_EDEVICE, "result copy failed");
+}
+
+fassmvs_status fassmvs_server_close_stream(fassmvs_server *s, int32_t stream_id) {
+    if (!s) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->streams.find(stream_id);
+    if (it == s->streams.end()) return sfail(s, FASSMVS_ENOTFOUND, "unknown stream");
+    it->second->closed = true;
+    it->second->keys.clear();
+    return FASSMVS_OK;
+}
+
+const char *fassmvs_server_last_error(const fassmvs_server *s) { return s ? s->err.c_str() : ""; }
+
+void fassmvs_server_destroy(fassmvs_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    hipSetDevice(s->cfg.device);
+    for (auto &r : s->done) give_maps(r);
+    for (auto &kv : s->fetched_pending) give_maps(kv.second);
+    for (auto &sl : s->slots) {
+        sl.req = Request();
+        if (sl.h) fassmvs_destroy(sl.h);
+        if (sl.stream) hipStreamDestroy(sl.stream);
+    }
+    for (auto &kv : s->streams) {
+        kv.second->keys.clear();
+        for (uint8_t *p : kv.second->pool) hipFree(p);
+        kv.second->pool.clear();
+        for (auto &m : kv.second->map_pool) {
+            hipFree(m.depth);
+            hipFree(m.normal);
+            hipFree(m.conf);
+        }
+        kv.second->map_pool.clear();
+    }
+    delete s;
+}
+
+}  // extern "C"

@@ -559,6 +559,25 @@ WORKLOADS = {
 }
 
 
+def served_stream(seed: int, w: int, h: int, n_frames: int, spacing: float = 0.5, planes: int = 128,
+                  n_boxes: int = 20, n_roofs: int = 5):
+    """One UAV stream of the served workload: n_frames along a smooth
+    oblique flight path, spacing metres apart (5 m/s at 10 Hz: 0.5 m), over
+    an independent urban scene (seed), fx = 1500 scaled to the width; 3
+    levels x planes fronto-parallel planes over [20, 400] m, census 9x7,
+    SGM^Pi-sn.  Returns K, frames [(img, R, t)], families, params."""
+    s = w / 1920.0
+    K, imgs, poses, ref_index, side, gt, scene, _ = oblique_urban(
+        seed, w, h, 1500.0 * s, n_frames - 1, n_boxes, n_roofs, spacing=(spacing, spacing))
+    fam = [dict(n=(0.0, 0.0, -1.0), delta_min=20.0, delta_max=400.0, count=planes)]
+    params = _params(n_levels=3, census_w=9, census_h=7, p1=24, p2_mode=1, sgm_variant=1, window_labels=planes)
+    frames = [(img, R, t) for img, (R, t) in zip(imgs, poses)]
+    return dict(K=K, width=w, height=h, frames=frames, families=fam, params=params)
+
+
+SERVED_STREAMS = [(200, 960, 540), (201, 1280, 720), (202, 1920, 1080), (203, 2704, 1520)]
+
+
 def with_cross_ratio_counts(wl):
     """The same bundle with every family's coarsest plane count left to the
     cross-ratio construction (count 0)."""
