@@ -61,6 +61,11 @@ def main():
     ap.add_argument("--host-io-steps", type=int, default=5,
                     help="after the timed region, run this many frames with host input/output buffers and report "
                          "that PCIe-inclusive rate beside the device-resident one")
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the served-vs-plain measurement on the four-stream trace")
+    ap.add_argument("--served-slots", type=int, default=4)
+    ap.add_argument("--served-frames", type=int, default=6, help="rendered frames per stream")
+    ap.add_argument("--served-repeats", type=int, default=5, help="passes over each stream's frames")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device once (a plain copy kernel of known "
                          "size whose HBM byte counters calibrate the profiler's FETCH_SIZE / WRITE_SIZE)")
@@ -72,6 +77,12 @@ def main():
 
     import scenegen
     import paper_2112_00821_amd as fm
+
+    # the served trace's streams are rendered on the CPU before the GPU is used
+    served_streams = None
+    if not args.no_served:
+        served_streams = [scenegen.served_stream(seed, w, h, args.served_frames)
+                          for seed, w, h in scenegen.SERVED_STREAMS]
 
     wl = scenegen.make_workload(args.workload)
     cfg = fm.config_from_params(wl["params"], profile=1)
@@ -176,10 +187,99 @@ def main():
         "roofline": roof,
         "sgm_roofline": sgm_roof,
     }
+    if served_streams is not None:
+        out["served"] = served_bench(fm, served_streams, args.served_slots, args.served_repeats)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out))
     return 0
+
+
+def _trace(streams, repeats, rate_hz=10.0, seed=300):
+    """Arrivals of every stream's frames at rate_hz with exponential jitter
+    (mean 5 ms); each stream's frames are replayed `repeats` times, every
+    pass as a fresh stream (its keyframes start over)."""
+    rng = np.random.default_rng(seed)
+    ev = []
+    for s, st in enumerate(streams):
+        F = len(st["frames"])
+        last = -1.0
+        for r in range(repeats):
+            for i in range(F):
+                t = (r * F + i) / rate_hz + rng.exponential(0.005)
+                t = max(t, last + 1e-3)
+                last = t
+                ev.append((t, s, r, i))
+    ev.sort()
+    return ev
+
+
+def _run_trace(fm, srv, streams, events, speed):
+    """Submit the trace to the server at its arrival times divided by speed
+    (speed 0: all at once).  Returns throughput and latency figures."""
+    import threading
+    sids = {}
+    expected = len(events)
+    done = []
+
+    def collect():
+        while len(done) < expected:
+            r = srv.next(-1)
+            r["t_done"] = time.perf_counter()
+            if r["status"] == fm.OK:
+                srv.fetch(r["request_id"], r["width"], r["height"])
+            done.append(r)
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    for (t, s, rep, i) in events:
+        if (s, rep) not in sids:
+            st = streams[s]
+            sids[(s, rep)] = srv.open_stream(st["K"], st["width"], st["height"], st["families"])
+        if speed > 0:
+            dt = t0 + t / speed - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+        srv.submit(sids[(s, rep)], *streams[s]["frames"][i])
+    th.join()
+    for sid in sids.values():
+        srv.close_stream(sid)
+    t_end = max(r["t_done"] for r in done)
+    ok = [r for r in done if r["status"] == fm.OK]
+    lat = np.array([r["latency_ms"] for r in ok])
+    span = t_end - t0
+    hyp = 0.0
+    for r in ok:
+        w, h = r["width"], r["height"]
+        hyp += sum((w >> l) * (h >> l) * 128 for l in range(3))
+    return {"frames": len(ok), "seconds": round(span, 3), "frames_per_s": round(len(ok) / span, 2),
+            "mpx_hyp_per_s": round(hyp / 1e6 / span, 1),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
+                           "p99": round(float(np.percentile(lat, 99)), 2),
+                           "max": round(float(lat.max()), 2)}}
+
+
+def served_bench(fm, streams, n_slots, repeats):
+    """Served vs plain on the four-stream trace: the same server with one
+    slot (the plain sequential per-frame pipeline) and with n_slots
+    concurrent slots.  After an untimed pass that sizes every buffer pool,
+    the trace runs at its real arrival rate (10 Hz per stream), twice as
+    fast, and all at once (sustained rate)."""
+    cfg = fm.config_from_params(streams[0]["params"])
+    events = _trace(streams, repeats)
+    out = {"streams": [f"{st['width']}x{st['height']}" for st in streams],
+           "trace": f"{len(events)} frames, 4 streams at 10 Hz (+exp. jitter, mean 5 ms), {repeats} passes of "
+                    f"{len(streams[0]['frames'])} rendered frames per stream, keyframe every 1 m at 0.5 m spacing, "
+                    f"up to 4 keyframes per bundle, 3 levels x 128 planes, census 9x7, SGM^Pi-sn",
+           "slots": n_slots}
+    for name, k in (("plain", 1), ("served", n_slots)):
+        with fm.Server(cfg, n_slots=k) as srv:
+            _run_trace(fm, srv, streams, events, 0)        # warm-up: allocations
+            out[name] = {"realtime": _run_trace(fm, srv, streams, events, 1.0),
+                         "x2": _run_trace(fm, srv, streams, events, 2.0),
+                         "saturated": _run_trace(fm, srv, streams, events, 0)}
+    return out
 
 
 def cpu_baseline(wl):

@@ -118,6 +118,7 @@ struct fassmvs_handle {
     int32_t stage_n[ST_COUNT] = {};
     double last_work[4] = {};
     unsigned long long sweep_work = 0;
+    unsigned long long *work_host = nullptr;   // pinned: the counter's copy must not block the submit
 };
 
 namespace {
@@ -1011,6 +1012,15 @@ fassmvs_status fassmvs_create(const fassmvs_config *cfg, fassmvs_handle **out) {
         g_create_error = "event creation failed";
         return FASSMVS_EDEVICE;
     }
+    if (hipHostMalloc((void **)&h->work_host, 64) != hipSuccess) {
+        (void)hipGetLastError();
+        hipEventDestroy(h->done);
+        if (h->own_stream) hipStreamDestroy(h->stream);
+        delete h;
+        g_create_error = "pinned counter allocation failed";
+        return FASSMVS_ENOMEM;
+    }
+    *h->work_host = 0;
     *out = h;
     return FASSMVS_OK;
 }
@@ -1052,7 +1062,7 @@ fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref,
         HIPCHK(h, hipMemcpyAsync(h->params.p, pb, P.blob.size() * 8, hipMemcpyHostToDevice, h->stream), "params");
     }
     if ((st = enqueue_frame(h, P)) != FASSMVS_OK) return st;
-    HIPCHK(h, hipMemcpyAsync(&h->sweep_work, h->work_ctr.p, 8, hipMemcpyDeviceToHost, h->stream), "work counter");
+    HIPCHK(h, hipMemcpyAsync(h->work_host, h->work_ctr.p, 8, hipMemcpyDeviceToHost, h->stream), "work counter");
     HIPCHK(h, hipEventRecord(h->done, h->stream), "event record");
     h->out_w = P.w;
     h->out_h = P.h;
@@ -1097,6 +1107,7 @@ fassmvs_status fassmvs_poll(fassmvs_handle *h, uint64_t ticket, float *depth, fl
     collect_timers(h);
     h->last_work[0] = h->plan.work_hyp;
     h->last_work[1] = h->plan.work_hyp_views;
+    h->sweep_work = *h->work_host;
     h->last_work[2] = (double)h->sweep_work;
     h->last_work[3] = h->plan.sgm_bytes;
     h->busy = false;
@@ -1123,6 +1134,7 @@ void fassmvs_destroy(fassmvs_handle *h) {
             release(L.label); release(L.fam); release(L.offs); release(L.dI); release(L.dbar); release(L.nbar);
         }
         if (h->pin) hipHostFree(h->pin);
+        if (h->work_host) hipHostFree(h->work_host);
         for (auto &t : h->pending_timers) {
             hipEventDestroy(t.a);
             hipEventDestroy(t.b);

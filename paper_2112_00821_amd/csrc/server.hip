@@ -8,9 +8,9 @@
 //
 // Host code over the library's public C ABI.  A worker thread admits
 // queued frames and collects finished ones; submit and result calls only
-// touch the queues.  Keyframe images stay on the device (per stream, a
-// pool of image buffers with reference counts held by the frames that use
-// them and by the keyframe list).
+// touch the queues.  Keyframe images stay on the device (pooled image
+// buffers, held by reference counts of the frames that use them and of the
+// keyframe list).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,11 +38,30 @@ double ms_since(Clock::time_point t0, Clock::time_point t1) {
 
 struct Stream;
 
-// A device copy of one frame's image, returned to its stream's pool when
-// the last user lets go.
+// A device copy of one frame's image (uploaded asynchronously through a
+// pinned staging buffer on the server's upload stream; `ready` marks the
+// end of the upload), returned to its stream's pool when the last user lets
+// go.
+struct ImageBuf {
+    uint8_t *p = nullptr;       // device
+    uint8_t *stage = nullptr;   // pinned host staging
+    hipEvent_t ready = nullptr;
+};
+struct MapBuf {
+    float *depth = nullptr, *normal = nullptr, *conf = nullptr;
+};
+// Free buffers of the server, by frame size (pixels): streams of the same
+// size share them, and nothing is freed before the server goes (hipFree
+// would synchronise the device and stall the frames in flight).
+struct Pools {
+    std::mutex mu;
+    std::map<size_t, std::vector<ImageBuf>> img;
+    std::map<size_t, std::vector<MapBuf>> maps;
+};
 struct DevImage {
-    uint8_t *p = nullptr;
-    Stream *owner = nullptr;
+    ImageBuf b;
+    size_t n = 0;
+    Pools *pools = nullptr;
     ~DevImage();
 };
 
@@ -59,19 +78,14 @@ struct Stream {
         double R[9], t[3], C[3];
     };
     std::deque<Key> keys;
-    std::vector<uint8_t *> pool;   // free device image buffers
-    struct Maps {
-        float *depth = nullptr, *normal = nullptr, *conf = nullptr;
-    };
-    std::vector<Maps> map_pool;    // free device result maps
-    std::mutex *pool_mu = nullptr;
+    Pools *pools = nullptr;
     bool closed = false;
 };
 
 DevImage::~DevImage() {
-    if (p && owner) {
-        std::lock_guard<std::mutex> lk(*owner->pool_mu);
-        owner->pool.push_back(p);
+    if (b.p && pools) {
+        std::lock_guard<std::mutex> lk(pools->mu);
+        pools->img[n].push_back(b);
     }
 }
 
@@ -88,26 +102,26 @@ struct Request {
 
 struct Result {
     fassmvs_server_result info;
-    Stream *owner = nullptr;
-    float *depth = nullptr, *normal = nullptr, *conf = nullptr;   // device, from owner's map pool
+    Pools *pools = nullptr;
+    float *depth = nullptr, *normal = nullptr, *conf = nullptr;   // device, from the map pool
 };
 
-// Result maps of a stream from its pool (allocated once; hipFree would
-// synchronise the device and stall the frames in flight).
+// Result maps of a frame size from the pool, allocated on first use.
 bool take_maps(Stream &st, Result &r) {
+    const size_t N = (size_t)st.w * st.h;
     {
-        std::lock_guard<std::mutex> lk(*st.pool_mu);
-        if (!st.map_pool.empty()) {
-            Stream::Maps m = st.map_pool.back();
-            st.map_pool.pop_back();
+        std::lock_guard<std::mutex> lk(st.pools->mu);
+        auto &v = st.pools->maps[N];
+        if (!v.empty()) {
+            MapBuf m = v.back();
+            v.pop_back();
             r.depth = m.depth;
             r.normal = m.normal;
             r.conf = m.conf;
-            r.owner = &st;
+            r.pools = st.pools;
             return true;
         }
     }
-    const size_t N = (size_t)st.w * st.h;
     float *d = nullptr, *n = nullptr, *c = nullptr;
     if (hipMalloc(&d, N * 4) != hipSuccess || hipMalloc(&n, N * 12) != hipSuccess || hipMalloc(&c, N * 4) != hipSuccess) {
         (void)hipGetLastError();
@@ -119,14 +133,14 @@ bool take_maps(Stream &st, Result &r) {
     r.depth = d;
     r.normal = n;
     r.conf = c;
-    r.owner = &st;
+    r.pools = st.pools;
     return true;
 }
 
 void give_maps(Result &r) {
-    if (!r.owner || !r.depth) return;
-    std::lock_guard<std::mutex> lk(*r.owner->pool_mu);
-    r.owner->map_pool.push_back(Stream::Maps{r.depth, r.normal, r.conf});
+    if (!r.pools || !r.depth) return;
+    std::lock_guard<std::mutex> lk(r.pools->mu);
+    r.pools->maps[(size_t)r.info.width * r.info.height].push_back(MapBuf{r.depth, r.normal, r.conf});
     r.depth = r.normal = r.conf = nullptr;
 }
 
@@ -146,7 +160,7 @@ struct fassmvs_server {
     uint64_t budget = 0, in_use = 0;
     std::vector<Slot> slots;
     std::map<int, std::unique_ptr<Stream>> streams;
-    std::mutex pool_mu;   // image and result-map pools of every stream
+    Pools pools;
     std::mutex mu;        // queues, streams, results
     std::condition_variable cv_work, cv_done;
     std::deque<Request> queue;
@@ -158,6 +172,8 @@ struct fassmvs_server {
     std::string err;
     std::thread worker;
     size_t in_flight = 0;
+    hipStream_t upload = nullptr, fetch = nullptr;   // non-blocking streams for image uploads and result copies
+    std::mutex fetch_mu;
 };
 
 namespace {
@@ -171,103 +187,127 @@ void camera_centre(const double *R, const double *t, double *C) {
     for (int i = 0; i < 3; ++i) C[i] = -(R[i] * t[0] + R[3 + i] * t[1] + R[6 + i] * t[2]);
 }
 
-// Admit the head of the queue into free slots while the footprint fits.
-// Called by the worker with s->mu held.
-void admit(fassmvs_server *s) {
-    while (!s->queue.empty()) {
-        Slot *free_slot = nullptr;
-        for (auto &sl : s->slots)
-            if (!sl.busy) {
-                free_slot = &sl;
-                break;
-            }
-        if (!free_slot) return;
-        Request &r = s->queue.front();
-        if (s->in_flight > 0 && s->in_use + r.footprint > s->budget) return;
-        Request req = std::move(r);
-        s->queue.pop_front();
-        Stream &st = *s->streams.at(req.stream);
-        Result res;
-        std::memset(&res.info, 0, sizeof(res.info));
-        res.info.request_id = req.id;
-        res.info.stream_id = req.stream;
-        res.info.width = st.w;
-        res.info.height = st.h;
-        res.info.keyframe = req.keyframe ? 1 : 0;
-        res.info.n_views = (int32_t)req.views.size();
-        if (req.views.empty()) {
-            // nothing to match against yet (first keyframe of a stream)
-            res.info.status = FASSMVS_ENOTFOUND;
-            res.info.latency_ms = ms_since(req.arrival, Clock::now());
-            s->done.push_back(res);
-            s->cv_done.notify_all();
-            continue;
+// Admit the head of the queue into a free slot if its footprint fits.
+// Called by the worker (which alone touches the slots) with lk held; the
+// lock is released while the frame is enqueued.  Returns true if a request
+// left the queue.
+bool admit_one(fassmvs_server *s, std::unique_lock<std::mutex> &lk) {
+    if (s->queue.empty()) return false;
+    Slot *free_slot = nullptr;
+    for (auto &sl : s->slots)
+        if (!sl.busy) {
+            free_slot = &sl;
+            break;
         }
-        if (!take_maps(st, res)) {
-            res.info.status = FASSMVS_ENOMEM;
-            s->done.push_back(res);
-            s->cv_done.notify_all();
-            continue;
-        }
-        fassmvs_image ref;
-        std::memset(&ref, 0, sizeof(ref));
-        ref.pixels = req.img->p;
-        ref.width = st.w;
-        ref.height = st.h;
-        ref.stride = st.w;
-        std::memcpy(ref.R, req.R, sizeof(ref.R));
-        std::memcpy(ref.t, req.t, sizeof(ref.t));
-        fassmvs_image views[FASSMVS_MAX_VIEWS];
-        int8_t side[FASSMVS_MAX_VIEWS];
-        const int nv = (int)req.views.size();
-        for (int k = 0; k < nv; ++k) {
-            std::memset(&views[k], 0, sizeof(views[k]));
-            views[k].pixels = req.views[k].img->p;
-            views[k].width = st.w;
-            views[k].height = st.h;
-            views[k].stride = st.w;
-            std::memcpy(views[k].R, req.views[k].R, sizeof(views[k].R));
-            std::memcpy(views[k].t, req.views[k].t, sizeof(views[k].t));
-            side[k] = -1;   // earlier in the sequence: one-sided bundle
-        }
-        uint64_t ticket = 0;
-        fassmvs_status rc = fassmvs_submit_frame(free_slot->h, &ref, views, side, nv, st.K, st.fams.data(),
-                                                 (int32_t)st.fams.size(), FASSMVS_MEM_DEVICE, &ticket);
-        if (rc != FASSMVS_OK) {
-            give_maps(res);
-            res.info.status = rc;
-            res.info.latency_ms = ms_since(req.arrival, Clock::now());
-            s->done.push_back(res);
-            s->cv_done.notify_all();
-            continue;
-        }
-        free_slot->busy = true;
-        free_slot->ticket = ticket;
-        free_slot->req = std::move(req);
-        free_slot->res = res;
-        s->in_use += free_slot->req.footprint;
-        s->in_flight++;
+    if (!free_slot) return false;
+    Request &head = s->queue.front();
+    if (s->in_flight > 0 && s->in_use + head.footprint > s->budget) return false;
+    Request req = std::move(head);
+    s->queue.pop_front();
+    Stream &st = *s->streams.at(req.stream);
+    Result res;
+    std::memset(&res.info, 0, sizeof(res.info));
+    res.info.request_id = req.id;
+    res.info.stream_id = req.stream;
+    res.info.width = st.w;
+    res.info.height = st.h;
+    res.info.keyframe = req.keyframe ? 1 : 0;
+    res.info.n_views = (int32_t)req.views.size();
+    if (req.views.empty()) {
+        // nothing to match against yet (first keyframe of a stream)
+        res.info.status = FASSMVS_ENOTFOUND;
+        res.info.latency_ms = ms_since(req.arrival, Clock::now());
+        s->done.push_back(res);
+        s->cv_done.notify_all();
+        return true;
     }
+    if (!take_maps(st, res)) {
+        res.info.status = FASSMVS_ENOMEM;
+        s->done.push_back(res);
+        s->cv_done.notify_all();
+        return true;
+    }
+    // reserve before enqueueing (the lock is dropped meanwhile)
+    free_slot->busy = true;
+    s->in_use += req.footprint;
+    s->in_flight++;
+    const double K[9] = {st.K[0], st.K[1], st.K[2], st.K[3], st.K[4], st.K[5], st.K[6], st.K[7], st.K[8]};
+    const std::vector<fassmvs_plane_family> fams = st.fams;
+    const int w = st.w, h = st.h;
+    lk.unlock();
+    // the slot's stream waits (on the device) for the images' uploads
+    hipStreamWaitEvent(free_slot->stream, req.img->b.ready, 0);
+    for (auto &v : req.views) hipStreamWaitEvent(free_slot->stream, v.img->b.ready, 0);
+    fassmvs_image ref;
+    std::memset(&ref, 0, sizeof(ref));
+    ref.pixels = req.img->b.p;
+    ref.width = w;
+    ref.height = h;
+    ref.stride = w;
+    std::memcpy(ref.R, req.R, sizeof(ref.R));
+    std::memcpy(ref.t, req.t, sizeof(ref.t));
+    fassmvs_image views[FASSMVS_MAX_VIEWS];
+    int8_t side[FASSMVS_MAX_VIEWS];
+    const int nv = (int)req.views.size();
+    for (int k = 0; k < nv; ++k) {
+        std::memset(&views[k], 0, sizeof(views[k]));
+        views[k].pixels = req.views[k].img->b.p;
+        views[k].width = w;
+        views[k].height = h;
+        views[k].stride = w;
+        std::memcpy(views[k].R, req.views[k].R, sizeof(views[k].R));
+        std::memcpy(views[k].t, req.views[k].t, sizeof(views[k].t));
+        side[k] = -1;   // earlier in the sequence: one-sided bundle
+    }
+    uint64_t ticket = 0;
+    fassmvs_status rc = fassmvs_submit_frame(free_slot->h, &ref, views, side, nv, K, fams.data(),
+                                             (int32_t)fams.size(), FASSMVS_MEM_DEVICE, &ticket);
+    lk.lock();
+    if (rc != FASSMVS_OK) {
+        give_maps(res);
+        res.info.status = rc;
+        res.info.latency_ms = ms_since(req.arrival, Clock::now());
+        free_slot->busy = false;
+        s->in_use -= req.footprint;
+        s->in_flight--;
+        s->done.push_back(res);
+        s->cv_done.notify_all();
+        return true;
+    }
+    free_slot->ticket = ticket;
+    free_slot->req = std::move(req);
+    free_slot->res = res;
+    return true;
 }
 
-// Collect finished frames (non-blocking).  s->mu held.
-bool collect(fassmvs_server *s) {
+// Collect finished frames (non-blocking).  lk held on entry and exit; the
+// maps' copy out of a finished slot runs without it.
+bool collect(fassmvs_server *s, std::unique_lock<std::mutex> &lk) {
     bool any = false;
     for (auto &sl : s->slots) {
-        if (!sl.busy) continue;
+        if (!sl.busy || sl.ticket == 0) continue;
+        lk.unlock();
         fassmvs_status rc = fassmvs_poll(sl.h, sl.ticket, sl.res.depth, sl.res.normal, sl.res.conf,
                                          FASSMVS_MEM_DEVICE, 0);
+        const Clock::time_point now = Clock::now();
+        Request finished;
+        if (rc != FASSMVS_PENDING) finished = std::move(sl.req);   // drop the image references outside the lock
+        lk.lock();
         if (rc == FASSMVS_PENDING) continue;
         Result res = sl.res;
         res.info.status = rc;
-        res.info.latency_ms = ms_since(sl.req.arrival, Clock::now());
+        res.info.latency_ms = ms_since(finished.arrival, now);
         if (rc != FASSMVS_OK) give_maps(res);
-        s->in_use -= sl.req.footprint;
+        s->in_use -= finished.footprint;
         s->in_flight--;
         sl.busy = false;
-        sl.req = Request();   // drop the image references
+        sl.ticket = 0;
+        sl.req = Request();
         s->done.push_back(res);
         any = true;
+        lk.unlock();
+        finished = Request();
+        lk.lock();
     }
     if (any) s->cv_done.notify_all();
     return any;
@@ -278,10 +318,8 @@ void worker_loop(fassmvs_server *s) {
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         if (s->stop && s->queue.empty() && s->in_flight == 0) break;
-        bool progress = collect(s);
-        const size_t before = s->queue.size();
-        admit(s);
-        progress |= s->queue.size() != before;
+        bool progress = collect(s, lk);
+        while (admit_one(s, lk)) progress = true;
         if (!progress) {
             if (s->in_flight > 0)
                 s->cv_work.wait_for(lk, std::chrono::microseconds(50));
@@ -309,6 +347,9 @@ fassmvs_status fassmvs_server_create(const fassmvs_config *cfg, int32_t n_slots,
         hbm_budget_bytes = (uint64_t)(fr * 0.8);
     }
     s->budget = hbm_budget_bytes;
+    if (hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->fetch, hipStreamNonBlocking) != hipSuccess)
+        return FASSMVS_EDEVICE;
     s->slots.resize(n_slots);
     for (auto &sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) return FASSMVS_EDEVICE;
@@ -343,7 +384,7 @@ fassmvs_status fassmvs_server_open_stream(fassmvs_server *s, const double K[9], 
     st->fams.assign(families, families + n_families);
     st->max_kf = max_keyframes;
     st->min_baseline = min_baseline;
-    st->pool_mu = &s->pool_mu;
+    st->pools = &s->pools;
     std::lock_guard<std::mutex> lk(s->mu);
     st->id = s->next_stream++;
     *stream_id = st->id;
@@ -367,24 +408,36 @@ fassmvs_status fassmvs_server_submit(fassmvs_server *s, int32_t stream_id, const
         if (!std::isfinite(R[i])) return sfail(s, FASSMVS_EINVAL, "non-finite pose");
     for (int i = 0; i < 3; ++i)
         if (!std::isfinite(t[i])) return sfail(s, FASSMVS_EINVAL, "non-finite pose");
-    // the image goes to the device now: every later frame of the stream that
-    // takes it as a keyframe finds it there
-    uint8_t *dp = nullptr;
+    // the image goes to the device now (asynchronously): every later frame
+    // of the stream that takes it as a keyframe finds it there
+    ImageBuf b;
+    const size_t N = (size_t)st->w * st->h;
     {
-        std::lock_guard<std::mutex> lk(s->pool_mu);
-        if (!st->pool.empty()) {
-            dp = st->pool.back();
-            st->pool.pop_back();
+        std::lock_guard<std::mutex> lk(s->pools.mu);
+        auto &v = s->pools.img[N];
+        if (!v.empty()) {
+            b = v.back();
+            v.pop_back();
         }
     }
-    if (!dp && hipMalloc(&dp, (size_t)st->w * st->h) != hipSuccess) {
-        (void)hipGetLastError();
-        return sfail(s, FASSMVS_ENOMEM, "image buffer allocation failed");
+    if (!b.p) {
+        if (hipMalloc(&b.p, N) != hipSuccess || hipHostMalloc(&b.stage, N) != hipSuccess ||
+            hipEventCreateWithFlags(&b.ready, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            if (b.p) hipFree(b.p);
+            if (b.stage) hipHostFree(b.stage);
+            return sfail(s, FASSMVS_ENOMEM, "image buffer allocation failed");
+        }
+    } else if (hipEventSynchronize(b.ready) != hipSuccess) {   // staging free again
+        return sfail(s, FASSMVS_EDEVICE, "image buffer reuse");
     }
+    for (int y = 0; y < st->h; ++y) std::memcpy(b.stage + (size_t)y * st->w, pixels + (size_t)y * stride, st->w);
     auto img = std::make_shared<DevImage>();
-    img->p = dp;
-    img->owner = st;
-    if (hipMemcpy2D(dp, st->w, pixels, stride, st->w, st->h, hipMemcpyHostToDevice) != hipSuccess)
+    img->b = b;
+    img->n = N;
+    img->pools = &s->pools;
+    if (hipMemcpyAsync(b.p, b.stage, N, hipMemcpyHostToDevice, s->upload) != hipSuccess ||
+        hipEventRecord(b.ready, s->upload) != hipSuccess)
         return sfail(s, FASSMVS_EDEVICE, "image upload failed");
     Request req;
     req.arrival = arrival;
@@ -461,10 +514,14 @@ fassmvs_status fassmvs_server_fetch(fassmvs_server *s, uint64_t request_id, floa
     }
     const size_t N = (size_t)r.info.width * r.info.height;
     const hipMemcpyKind kind = mem_kind == FASSMVS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    // copies on the server's own non-blocking stream: they wait for nothing
+    // but themselves, frames in flight keep running
+    std::lock_guard<std::mutex> flk(s->fetch_mu);
     hipError_t e = hipSuccess;
-    if (depth && e == hipSuccess) e = hipMemcpy(depth, r.depth, N * 4, kind);
-    if (normal && e == hipSuccess) e = hipMemcpy(normal, r.normal, N * 12, kind);
-    if (confidence && e == hipSuccess) e = hipMemcpy(confidence, r.conf, N * 4, kind);
+    if (depth && e == hipSuccess) e = hipMemcpyAsync(depth, r.depth, N * 4, kind, s->fetch);
+    if (normal && e == hipSuccess) e = hipMemcpyAsync(normal, r.normal, N * 12, kind, s->fetch);
+    if (confidence && e == hipSuccess) e = hipMemcpyAsync(confidence, r.conf, N * 4, kind, s->fetch);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->fetch);
     give_maps(r);
     return e == hipSuccess ? FASSMVS_OK : sfail(s, FASSMVS_EDEVICE, "result copy failed");
 }
@@ -497,17 +554,22 @@ void fassmvs_server_destroy(fassmvs_server *s) {
         if (sl.h) fassmvs_destroy(sl.h);
         if (sl.stream) hipStreamDestroy(sl.stream);
     }
-    for (auto &kv : s->streams) {
-        kv.second->keys.clear();
-        for (uint8_t *p : kv.second->pool) hipFree(p);
-        kv.second->pool.clear();
-        for (auto &m : kv.second->map_pool) {
+    for (auto &kv : s->streams) kv.second->keys.clear();
+    for (auto &kv : s->pools.img)
+        for (ImageBuf &b : kv.second) {
+            hipEventSynchronize(b.ready);
+            hipEventDestroy(b.ready);
+            hipHostFree(b.stage);
+            hipFree(b.p);
+        }
+    for (auto &kv : s->pools.maps)
+        for (MapBuf &m : kv.second) {
             hipFree(m.depth);
             hipFree(m.normal);
             hipFree(m.conf);
         }
-        kv.second->map_pool.clear();
-    }
+    if (s->upload) hipStreamDestroy(s->upload);
+    if (s->fetch) hipStreamDestroy(s->fetch);
     delete s;
 }
 
