@@ -12,6 +12,9 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfassmvs.so")
 SOURCES = ["k_image.hip", "k_sweep.hip", "k_sgm.hip", "k_post.hip", "runtime.hip", "server.hip"]
+# sweep variants (window width, height, cost: 0 census, 1 NCC), one object
+# each from k_sweep_inst.hip so they compile in parallel
+SWEEP_VARIANTS = [(5, 5, 0), (9, 7, 0), (7, 7, 0), (3, 3, 0), (5, 5, 1), (9, 9, 1), (7, 7, 1), (3, 3, 1)]
 ARCH = os.environ.get("FASSMVS_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -27,9 +30,18 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _units():
+    units = [(src, os.path.splitext(src)[0], []) for src in SOURCES]
+    for cw, ch, cost in SWEEP_VARIANTS:
+        units.append(("k_sweep_inst.hip", f"k_sweep_{cw}x{ch}_{cost}",
+                      [f"-DFMVS_CW={cw}", f"-DFMVS_CH={ch}", f"-DFMVS_COST={cost}"]))
+    return units
+
+
+def _compile(unit) -> str:
+    src, name, defs = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC, *CFLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-6000:]}")
@@ -38,8 +50,11 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    units = _units()
+    # heaviest first: the sweep variants and the SGM dominate the build
+    order = sorted(units, key=lambda u: (u[0] not in ("k_sweep_inst.hip", "k_sgm.hip"), u[1]))
+    with ThreadPoolExecutor(max_workers=min(len(order), os.cpu_count() or 8)) as ex:
+        objs = list(ex.map(_compile, order))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
            "-Wl,-rpath,/opt/rocm/lib"]

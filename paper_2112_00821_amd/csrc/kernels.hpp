@@ -40,7 +40,7 @@ struct SweepArgs {
     const float *warped;      // [n_views][sumG][h][w] or nullptr
     uint8_t *S;               // [h][w][D]
     int tiles_x, tiles_y, n_chunks;
-    int rows_per_thread;      // 4 (tile 64x16) or 8 (tile 64x32)
+    int rows_per_thread;      // 4 (tile 64x16), 8 (tile 64x32), 0 = by cost
     unsigned long long *work; // optional counter of evaluated (pixel, label) pairs
 };
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t s);

@@ -219,14 +219,13 @@ void collect_timers(fassmvs_handle *h) {
     h->pending_timers.clear();
 }
 
-// Sweep tuning knob: FASSMVS_SWEEP_ROWS = 4 or 8 rows per thread (tile 64x16
-// or 64x32).  It changes the schedule only, never the result.
+// Sweep tuning knob, read at every launch: FASSMVS_SWEEP_ROWS = 4 or 8 rows
+// per thread (tile 64x16 or 64x32).  Unset, the launcher picks 8 for census
+// and 4 for NCC.  It changes the schedule only, never the result.
 int sweep_rows() {
-    static int v = [] {
-        const char *e = std::getenv("FASSMVS_SWEEP_ROWS");
-        return (e && std::atoi(e) == 4) ? 4 : 8;
-    }();
-    return v;
+    const char *e = std::getenv("FASSMVS_SWEEP_ROWS");
+    const int r = e ? std::atoi(e) : 0;
+    return (r == 4 || r == 8) ? r : 0;
 }
 
 

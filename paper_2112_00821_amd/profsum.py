@@ -26,7 +26,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # sources each timed kernel is built from (the hash marks the counters stale
 # once any of them changes)
 KERNEL_SOURCES = {
-    "k_sweep": ["csrc/k_sweep.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
+    "k_sweep": ["csrc/k_sweep.hpp", "csrc/k_sweep.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
     "k_sgm": ["csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
     "k_wta16": ["csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
 }

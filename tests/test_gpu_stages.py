@@ -109,7 +109,9 @@ def test_cost_from_oracle_warps_bit_exact(orc, hd, name):
 
 
 @pytest.mark.parametrize("name", ["config1", "config2_small", "config2_ragged", "config3_small"])
-def test_cost_volume_from_images(orc, hd, name):
+@pytest.mark.parametrize("rows", ["4", "8"])
+def test_cost_volume_from_images(orc, hd, monkeypatch, name, rows):
+    monkeypatch.setenv("FASSMVS_SWEEP_ROWS", rows)
     wl = scenegen.make_workload(name)
     p = wl["params"]
     level = p["n_levels"] - 1
