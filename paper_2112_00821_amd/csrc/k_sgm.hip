@@ -24,6 +24,9 @@ namespace fmvs {
 namespace {
 constexpr uint32_t INF = 0x3FFFFFFFu;
 constexpr int WAVES = 4;
+// cache-policy bit of the buffer intrinsics for non-temporal (streaming)
+// accesses on gfx950
+constexpr int kNonTemporal = 2;
 constexpr int GUARD = 3;
 constexpr int LBUF = kMaxLabels + 2 * GUARD * kMaxFam;
 
@@ -313,6 +316,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
     constexpr int G2 = 6;
     constexpr int LW = (kMaxLabels + 2 * G2 * kMaxFam) / 2 + 1;   // 32-bit words per buffer, last one a sink
     __shared__ uint32_t lbuf[WAVES][2][LW];
+    __shared__ int s_lut[256];   // P2 by intensity change
+    for (int i = threadIdx.x; i < 256; i += 64 * WAVES) s_lut[i] = a.lut[i];
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int path = blockIdx.x * WAVES + wid;
@@ -358,28 +364,51 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
     const uint8_t *__restrict__ S = a.S;
     uint16_t *__restrict__ out = a.out[slot];
 
-    auto load_chunk = [&](int t0, int &ref_v, int (&off_v)[NF], int (&di_v)[NF]) {
-        // ref_v: the penalty P2 of step t = t0 + lane, from the intensity
-        // step between its pixel and the previous one on the path
-        const int t = t0 + lane < len ? t0 + lane : len - 1;
+    // Uniform per-step values of one block of PF steps, one vector load per
+    // quantity (lane j holds step t0 + j, j < PF): the penalty P2 of the
+    // intensity change from the previous pixel, the window offsets and the
+    // surface-normal offsets.  The loads of a block are issued one block
+    // ahead and finished (the P2 lookup in LDS) when the block starts, so no
+    // load is waited for before its use.  The first step of the path gets
+    // P2 = 0: with the predecessor minimum at 0 the recursion then reduces
+    // to L = S there, so the first step needs no code of its own.
+    struct BlockRaw {
+        int i0, i1;   // intensities at the step and at its predecessor
+        bool first;
+        int off[NF], di[NF];
+    };
+    auto issue_block = [&](int t0, BlockRaw &r) {
+        const int tl = t0 + (lane & (PF - 1));
+        const int t = tl < len ? tl : len - 1;
         const long p = p0 + (long)t * pstride;
         const long pp = p0 + (long)(t > 0 ? t - 1 : 0) * pstride;
-        const int di = (int)a.ref[p] - (int)a.ref[pp];
-        ref_v = a.lut[di < 0 ? -di : di];
+        r.i0 = a.ref[p];
+        r.i1 = a.ref[pp];
+        r.first = t == 0;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            off_v[f] = (WIN && f < F) ? a.offs[(size_t)f * N + p] : 0;
-            di_v[f] = (SN && f < F) ? (int)a.dI[((size_t)dir * N + p) * F + f] : 0;
+            r.off[f] = (WIN && f < F) ? a.offs[(size_t)f * N + p] : 0;
+            r.di[f] = (SN && f < F) ? (int)a.dI[((size_t)dir * N + p) * F + f] : 0;
         }
     };
-    int c_ref, n_ref;
-    int c_off[NF], n_off[NF], c_di[NF], n_di[NF];
-    load_chunk(0, c_ref, c_off, c_di);
-    if (len > 64) load_chunk(64, n_ref, n_off, n_di);
+    int c_ref;
+    int c_off[NF], c_di[NF];
+    auto finish_block = [&](const BlockRaw &r) {
+        const int d = r.i0 - r.i1;
+        c_ref = r.first ? 0 : s_lut[d < 0 ? -d : d];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            c_off[f] = r.off[f];
+            c_di[f] = r.di[f];
+        }
+    };
+    BlockRaw raw;
+    issue_block(0, raw);
+    finish_block(raw);
 
     // ring of cost byte pairs, PF steps ahead (steps past the path's end
     // re-read its last pixel)
-    uint32_t ring[PF][KP];
+    uint16_t ring[PF][KP];
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         const long p = p0 + (long)(u < len ? u : len - 1) * pstride;
@@ -394,39 +423,58 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) oq[f] = 0;
 
-    // one step of the recursion at path position t (ring slot u)
-    auto step = [&](const int t, const int u, const int lb, const bool first) __attribute__((always_inline)) {
-        // PF divides 64, so the 64-step chunk of t is the current one
-        const long p = p0 + (long)t * pstride;
+    // Row pointers advance by one path step at a time (two scalar adds)
+    // instead of being recomputed from the step index: s_ahead is the cost
+    // row the ring loads next (PF steps ahead, held at the path's last
+    // pixel), o_cur the output row of the current step.
+    const long sstride = pstride * D;
+    const uint8_t *s_ahead = S + (size_t)(p0 + (long)(PF < len ? PF : len - 1) * pstride) * D;
+    uint16_t *o_cur = out + (size_t)p0 * D;
+
+    // one step of the recursion at path position t (ring slot and block
+    // lane u); clamp: the ring row may reach the path's last pixel in this
+    // step (else it advances unconditionally)
+    auto step = [&](const int t, const int u, const bool clamp) __attribute__((always_inline)) {
         u16x2 sv[KP];
 #pragma unroll
         for (int k = 0; k < KP; ++k) sv[k] = as_u16x2(__builtin_amdgcn_perm(0u, ring[u][k], 0x0c010c00u));
         {
-            const int tn = t + PF < len ? t + PF : len - 1;
-            const __amdgpu_buffer_rsrc_t rs = row_rsrc(S + (size_t)(p0 + (long)tn * pstride) * D, D);
+            // the reload of ring[u] may not move above its use (an empty
+            // asm that takes sv and yields the offset), so the slot keeps
+            // one register across the loop
+            uint32_t off[KP];
 #pragma unroll
-            for (int k = 0; k < KP; ++k) ring[u][k] = __builtin_amdgcn_raw_buffer_load_b16(rs, lo8[k], 0, 0);
+            for (int k = 0; k < KP; ++k) {
+                off[k] = lo8[k];
+                asm volatile("" : "+v"(off[k]) : "v"(sv[k]));
+            }
+            const __amdgpu_buffer_rsrc_t rs = row_rsrc(s_ahead, D);
+#pragma unroll
+            for (int k = 0; k < KP; ++k) ring[u][k] = __builtin_amdgcn_raw_buffer_load_b16(rs, off[k], 0, 0);
+            if (!clamp || t + PF + 1 < len) s_ahead += sstride;
+            // one live row pointer (the compiler would otherwise keep a
+            // precomputed address per unrolled step in scalar registers)
+            asm volatile("" : "+s"(s_ahead));
         }
-        const uint32_t P2 = (uint32_t)__builtin_amdgcn_readlane(c_ref, lb + u);
+        const uint32_t P2 = (uint32_t)__builtin_amdgcn_readlane(c_ref, u);
         int op[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) op[f] = WIN ? __builtin_amdgcn_readlane(c_off[f], lb + u) : 0;
+        for (int f = 0; f < NF; ++f) op[f] = WIN ? __builtin_amdgcn_readlane(c_off[f], u) : 0;
         uint32_t *cur = (u & 1) ? buf1 : buf0;
         const uint32_t *prev = (u & 1) ? buf0 : buf1;
-        if (first) {
-#pragma unroll
-            for (int k = 0; k < KP; ++k) L[k] = sv[k];
-        } else {
+        {
+            // splats of uniform 16-bit values (the packed instructions take
+            // them as one scalar operand)
             const uint32_t P1 = (uint32_t)a.p1;
-            const u16x2 p1v = as_u16x2(P1 | (P1 << 16));
-            const u16x2 mqv = as_u16x2(Mq | (Mq << 16));
-            const uint32_t fl = Mq + P2;
-            const u16x2 flv = as_u16x2(fl | (fl << 16));
+            const u16x2 p1v = (u16x2)(uint16_t)P1;
+            const u16x2 mqv = (u16x2)(uint16_t)Mq;
+            const uint16_t fl = (uint16_t)(Mq + P2);
+            const u16x2 flv = (u16x2)fl;
             int sh[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 int v = WIN ? op[f] - oq[f] : 0;
-                if (SN) v += __builtin_amdgcn_readlane(c_di[f], lb + u);
+                if (SN) v += __builtin_amdgcn_readlane(c_di[f], u);
                 sh[f] = v;
             }
 #pragma unroll
@@ -439,23 +487,21 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
                 const int sg = NF == 1 ? G2 : seg[k];
                 const int j = min(max(li[k] + sft, -4), jm);
                 const int base = sg + j;
-                // one family: every lane shares the shift's parity (the
-                // clamp bounds are even and read only guards either way)
-                const bool odd = NF == 1 ? (sft & 1) : (base & 1);
-                uint32_t wm, w0, wp;
-                if (odd) {
-                    const int e = (base - 1) >> 1;
-                    const uint32_t Y = prev[e], Z = prev[e + 1];
-                    wm = Y;
-                    w0 = __builtin_amdgcn_alignbit(Z, Y, 16);
-                    wp = Z;
-                } else {
-                    const int e = base >> 1;
-                    const uint32_t X = prev[e - 1], Y = prev[e], Z = prev[e + 1];
-                    wm = __builtin_amdgcn_alignbit(Y, X, 16);
-                    w0 = Y;
-                    wp = __builtin_amdgcn_alignbit(Z, Y, 16);
-                }
+                // The taps (j-1, j), (j, j+1), (j+1, j+2) of the pair are the
+                // 16-bit entries q .. q+3, q = base - 1, of three aligned
+                // words A, B, C; byte permutes pick them whatever the
+                // parity of q.  One family: every lane shares that parity
+                // (the shift's); where j is clamped the words hold guards
+                // only, so the choice does not matter there.
+                const int q = base - 1;
+                const uint32_t qodd = NF == 1 ? (uint32_t)((sft & 1) ^ 1) : (uint32_t)(q & 1);
+                const uint32_t s1 = 0x03020100u + qodd * 0x02020202u;
+                const uint32_t s2 = s1 + 0x02020202u;
+                const int e0 = q >> 1;
+                const uint32_t A = prev[e0], B = prev[e0 + 1], C = prev[e0 + 2];
+                const uint32_t wm = __builtin_amdgcn_perm(B, A, s1);
+                const uint32_t w0 = __builtin_amdgcn_perm(B, A, s2);
+                const uint32_t wp = __builtin_amdgcn_perm(C, B, s1);
                 const u16x2 cm = as_u16x2(wm), c0 = as_u16x2(w0), cp = as_u16x2(wp);
                 const u16x2 c1 = __builtin_elementwise_add_sat(__builtin_elementwise_min(cm, cp), p1v);
                 u16x2 best = __builtin_elementwise_min(c0, c1);
@@ -464,11 +510,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
             }
         }
         u16x2 m2 = as_u16x2(0xFFFFFFFFu);
-        const __amdgpu_buffer_rsrc_t ro = row_rsrc(out + (size_t)p * D, 2 * D);
+        const __amdgpu_buffer_rsrc_t ro = row_rsrc(o_cur, 2 * D);
+        o_cur += sstride;
+        asm volatile("" : "+s"(o_cur));
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
             cur[widx[k]] = as_u32(L[k]);
-            __builtin_amdgcn_raw_buffer_store_b32(as_u32(L[k]), ro, 2 * lo8[k], 0, 0);
+            // non-temporal: the path costs are read once, by the
+            // winner-takes-all pass, long after the caches have turned over
+            __builtin_amdgcn_raw_buffer_store_b32(as_u32(L[k]), ro, 2 * lo8[k], 0, kNonTemporal);
             m2 = __builtin_elementwise_min(m2, (all_valid || lv[k]) ? L[k] : as_u16x2(0xFFFFFFFFu));
         }
         __builtin_amdgcn_wave_barrier();
@@ -479,27 +529,27 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
         for (int f = 0; f < NF; ++f) oq[f] = op[f];
     };
 
-    for (int t0 = 0; t0 < len; t0 += PF) {
-        if (t0 > 0 && (t0 & 63) == 0) {
-            c_ref = n_ref;
+    // Whole blocks of PF steps, then the tail.  The loop body is one
+    // straight run of PF steps, so every ring slot and block value keeps its
+    // register from one block to the next and no load is waited for before
+    // its use PF steps later.
+    int t0 = 0;
+    for (; t0 + 2 * PF + 1 <= len; t0 += PF) {
+        issue_block(t0 + PF, raw);
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                c_off[f] = n_off[f];
-                c_di[f] = n_di[f];
-            }
-            if (t0 + 64 < len) load_chunk(t0 + 64, n_ref, n_off, n_di);
-        }
-        const int lb = t0 & 63;   // PF divides 64
-        if (t0 > 0 && t0 + PF <= len) {
+        for (int u = 0; u < PF; ++u) step(t0 + u, u, false);
+        finish_block(raw);
+    }
+    for (; t0 + PF <= len; t0 += PF) {
+        issue_block(t0 + PF, raw);
 #pragma unroll
-            for (int u = 0; u < PF; ++u) step(t0 + u, u, lb, false);
-        } else {
+        for (int u = 0; u < PF; ++u) step(t0 + u, u, true);
+        finish_block(raw);
+    }
 #pragma unroll
-            for (int u = 0; u < PF; ++u) {
-                if (t0 + u >= len) break;
-                step(t0 + u, u, lb, t0 + u == 0);
-            }
-        }
+    for (int u = 0; u < PF; ++u) {
+        if (t0 + u >= len) break;
+        step(t0 + u, u, true);
     }
 }
 
