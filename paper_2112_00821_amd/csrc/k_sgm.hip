@@ -633,6 +633,8 @@ __global__ __launch_bounds__(256) void k_wta16(const SgmArgs a) {
     const int nch = D >> 3;
     const size_t waves = (size_t)gridDim.x * 4;
     const size_t wid = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const size_t vol_bytes = N * D * 2;
+    const bool rsrc_ok = vol_bytes < ((size_t)1 << 32);
     for (size_t pb = wid * 4; pb < N; pb += waves * 4) {
         const size_t p = pb + row;
         const bool pv = p < N;
@@ -646,7 +648,18 @@ __global__ __launch_bounds__(256) void k_wta16(const SgmArgs a) {
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 if (b < a.n_in && cv) {
-                    const uint4 v = *(const uint4 *)(a.in[b] + p * D + 8 * c);
+                    // each path cost is read once: non-temporal load
+                    // through a buffer resource over the whole volume
+                    // (32-bit byte offsets), else a plain load
+                    uint4 v;
+                    if (rsrc_ok) {
+                        const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+                            const_cast<uint16_t *>(a.in[b]), 0, (int)(uint32_t)vol_bytes, 0x00020000);
+                        v = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                          rb, (uint32_t)((p * D + 8 * c) * 2), 0, kNonTemporal));
+                    } else {
+                        v = *(const uint4 *)(a.in[b] + p * D + 8 * c);
+                    }
                     s4[0] += __builtin_bit_cast(ushort2_t, v.x);
                     s4[1] += __builtin_bit_cast(ushort2_t, v.y);
                     s4[2] += __builtin_bit_cast(ushort2_t, v.z);
