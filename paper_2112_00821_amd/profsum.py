@@ -28,6 +28,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
     "k_sweep": ["csrc/k_sweep.hpp", "csrc/k_sweep.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
     "k_sgm": ["csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
+    "k_sgm_pk": ["csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
     "k_wta16": ["csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
 }
 
@@ -94,15 +95,17 @@ def main():
     ap.add_argument("--write")
     ap.add_argument("--sq")
     ap.add_argument("--bench")
-    ap.add_argument("--kernel", default="k_sweep")
+    ap.add_argument("--kernel", action="append", default=[],
+                    help="kernel(s) whose traffic record the summary carries (default k_sweep)")
     ap.add_argument("--copy-mb", type=int, default=256)
     ap.add_argument("--workload", default="")
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
 
+    kernels = a.kernel or ["k_sweep"]
     stats = read_stats(a.trace)
-    lines = [f"# {a.kernel}: {a.workload}", "", "Commands (run from the repository root):", ""]
+    lines = [f"# {', '.join(kernels)}: {a.workload}", "", "Commands (run from the repository root):", ""]
     lines += [f"    {c}" for c in a.command]
     lines += ["", "## Kernel time (rocprofv3 --kernel-trace --stats)", "",
               "| kernel | calls | avg ms | total ms | % |", "|---|---|---|---|---|"]
@@ -161,13 +164,18 @@ def main():
         js = json.loads([l for l in txt if l.startswith("{")][-1])
         lines += ["", "## Bench line of the same build", "", "    " + json.dumps(js)]
 
-    dom = [k for k in traffic if _base(k) == a.kernel]
-    if dom:
-        rec = {"kernel": a.kernel, "source_hash": source_hash(a.kernel),
-               "traffic_bytes_per_launch": traffic[dom[0]]["bytes"],
-               "fetch_bytes_per_launch": traffic[dom[0]]["fetch_bytes"],
-               "write_bytes_per_launch": traffic[dom[0]]["write_bytes"]}
-        lines += ["", "## Traffic record read by bench.py", "", "traffic_json: " + json.dumps(rec)]
+    recs = []
+    for kern in kernels:
+        # the instantiation with the most traffic stands for the kernel
+        dom = sorted((k for k in traffic if _base(k) == kern), key=lambda k: -traffic[k]["bytes"])
+        if dom:
+            recs.append({"kernel": kern, "instantiation": dom[0], "source_hash": source_hash(kern),
+                         "traffic_bytes_per_launch": traffic[dom[0]]["bytes"],
+                         "fetch_bytes_per_launch": traffic[dom[0]]["fetch_bytes"],
+                         "write_bytes_per_launch": traffic[dom[0]]["write_bytes"]})
+    if recs:
+        lines += ["", "## Traffic records read by bench.py", ""]
+        lines += ["traffic_json: " + json.dumps(r) for r in recs]
     with open(a.out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
