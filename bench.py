@@ -40,6 +40,7 @@ SGM_ALG_BYTES = 12.0
 # and read once by the streaming winner-takes-all (2 x 8 x 2 B)
 SGM_DESIGN_BYTES = 40.0
 PROFILE = os.path.join(ROOT, "profiles", "k_sweep_config2.md")
+SGM_PROFILE = os.path.join(ROOT, "profiles", "k_sgm_pk_config2.md")
 
 WORKLOADS = {
     "config2": ("1920x1080 oblique urban scene, reference + 4 views (2 left, 2 right), 3 levels x 128 "
@@ -167,6 +168,12 @@ def main():
                 "achieved_design": SGM_DESIGN_BYTES * hyp / (sgm_ms / 1e3) / 1e9}
     sgm_roof["frac_alg"] = sgm_roof["achieved_alg"] / PEAK_HBM_GBS
     sgm_roof["frac_design"] = sgm_roof["achieved_design"] / PEAK_HBM_GBS
+    # counted HBM bytes per launch of the aggregation and WTA kernels, from
+    # the committed profile while their sources are unchanged
+    if args.workload == "config2":
+        for kern in ("k_sgm_pk", "k_wta16"):
+            tr = profsum.read_traffic(SGM_PROFILE, kern)
+            sgm_roof[f"traffic_{kern}"] = tr["traffic_bytes_per_launch"] if tr else None
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpx·hyp/s", "n_gpus": 1, "steps": args.steps,

@@ -539,6 +539,29 @@ def nadir_planar(seed: int = 7, w: int = 160, h: int = 120):
     return wl
 
 
+CONFIG4_SIZES = [(640, 480), (960, 540), (1280, 720), (1920, 1080)]
+CONFIG4_SEEDS = list(range(100, 116))
+
+
+def config4_frame(seed: int):
+    """One frame of the uneven batch: resolution drawn from four UAV video
+    sizes, 2-5 matching views (split as evenly as possible, the extra one on
+    the left), 64-192 planes per level in steps of 8 over [20, 400] m (the
+    window at finer levels as wide as the top list), 2 or 3 pyramid levels;
+    census 9x7, SGM^Pi-sn, adaptive P2; an independent urban scene per seed."""
+    rng = np.random.default_rng(seed)
+    w, h = CONFIG4_SIZES[int(rng.integers(len(CONFIG4_SIZES)))]
+    n_views = int(rng.integers(2, 6))
+    planes = 8 * int(rng.integers(8, 25))
+    levels = int(rng.integers(2, 4))
+    s = w / 1920.0
+    K, imgs, poses, ref_index, side, gt, scene, _ = oblique_urban(seed, w, h, 1500.0 * s, n_views, 40, 10)
+    fam = [dict(n=(0.0, 0.0, -1.0), delta_min=20.0, delta_max=400.0, count=planes)]
+    params = _params(n_levels=levels, census_w=9, census_h=7, p1=24, p2_mode=1, sgm_variant=1,
+                     window_labels=planes)
+    return _pack(f"config4_{seed}", K, w, h, imgs, poses, ref_index, side, fam, params, gt, scene)
+
+
 WORKLOADS = {
     "config1": lambda: config1(0),
     "config2": lambda: config2(1),
@@ -554,6 +577,7 @@ WORKLOADS = {
     "config2_small_ncc": lambda: with_ncc(config2(1, 320, 184, planes=32, window=32)),
     "config2_ncc": lambda: with_ncc(config2(1)),
     # plane counts from the cross-ratio construction (count 0)
+    **{f"config4_{sd}": (lambda sd=sd: config4_frame(sd)) for sd in CONFIG4_SEEDS},
     "config1_xr": lambda: with_cross_ratio_counts(config1(0)),
     "config2_small_xr": lambda: with_cross_ratio_counts(config2(1, 320, 184, planes=32, window=32)),
 }
