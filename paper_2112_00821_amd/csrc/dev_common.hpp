@@ -35,8 +35,11 @@ __device__ __forceinline__ float warp_sample(const uint8_t *__restrict__ src, in
     sx = __builtin_fmin(__builtin_fmax(sx, 0.0), (double)(sw - 1));
     sy = __builtin_fmin(__builtin_fmax(sy, 0.0), (double)(sh - 1));
     const uint32_t xa = (uint32_t)(int)sx, ya = (uint32_t)(int)sy;
-    const float ax = (float)(sx - floor(sx));
-    const float ay = (float)(sy - floor(sy));
+    // fraction of a non-negative coordinate: exactly sx - floor(sx) (the
+    // fract instruction is correctly rounded and the difference is
+    // representable)
+    const float ax = (float)__builtin_amdgcn_fract(sx);
+    const float ay = (float)__builtin_amdgcn_fract(sy);
     const uint32_t xb = min(xa + 1u, (uint32_t)(sw - 1)), yb = min(ya + 1u, (uint32_t)(sh - 1));
     const uint32_t ra = __umul24(ya, (uint32_t)sw), rb = __umul24(yb, (uint32_t)sw);
     const float i00 = (float)src[ra + xa];

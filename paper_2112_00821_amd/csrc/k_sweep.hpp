@@ -54,29 +54,24 @@ __device__ __forceinline__ int combine_lr(int sL, int sR, int nL, int nR, int m)
     return best;
 }
 
-// Warp the tile region onto the reference grid into LDS.  tqx / tqy hold the
-// (clamped) pixel-centre coordinates of the region's columns and rows, so
-// the halo replicates the image border.
-template <int RW, int NS>
+// Warp the tile region onto the reference grid into LDS.  tq holds the
+// (clamped) pixel-centre coordinates of every region sample (exact in
+// float), so the halo replicates the image border and a thread's sample i
+// is one LDS read at a fixed offset.
+template <int NS>
 __device__ __forceinline__ void warp_region(float *buf, const uint8_t *__restrict__ src, int w, int h,
-                                            const double *tqx, const double *tqy, int tid, double h0, double h1,
-                                            double h2, double h3, double h4, double h5, double h6, double h7,
-                                            double h8) {
+                                            const float2 *tq, int tid, double h0, double h1, double h2, double h3,
+                                            double h4, double h5, double h6, double h7, double h8) {
     constexpr int NFULL = NS / NT;
-    constexpr int DRY = NT / RW, DRX = NT % RW;
-    int ry = tid / RW, rx = tid - (tid / RW) * RW;
 #pragma unroll 2
     for (int i = 0; i < NFULL; ++i) {
-        buf[tid + i * NT] = warp_sample(src, w, h, h0, h1, h2, h3, h4, h5, h6, h7, h8, tqx[rx], tqy[ry]);
-        rx += DRX;
-        ry += DRY;
-        if (rx >= RW) {
-            rx -= RW;
-            ry += 1;
-        }
+        const float2 q = tq[tid + i * NT];
+        buf[tid + i * NT] = warp_sample(src, w, h, h0, h1, h2, h3, h4, h5, h6, h7, h8, (double)q.x, (double)q.y);
     }
-    if (NS % NT != 0 && tid + NFULL * NT < NS)
-        buf[tid + NFULL * NT] = warp_sample(src, w, h, h0, h1, h2, h3, h4, h5, h6, h7, h8, tqx[rx], tqy[ry]);
+    if (NS % NT != 0 && tid + NFULL * NT < NS) {
+        const float2 q = tq[tid + NFULL * NT];
+        buf[tid + NFULL * NT] = warp_sample(src, w, h, h0, h1, h2, h3, h4, h5, h6, h7, h8, (double)q.x, (double)q.y);
+    }
 }
 }  // namespace
 
@@ -105,7 +100,7 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
     constexpr int NS = RW * RH;
     __shared__ float wbuf[2][NS];
     __shared__ double aref[COST == 1 ? NS : 1];   // reference intensities of the region (NCC)
-    __shared__ double tqx[RW], tqy[RH];
+    __shared__ float2 tq[NS];   // sample coordinates of the region
     __shared__ int s_lo[kMaxFam], s_hi[kMaxFam];
 
     // XCD-aware remap: hardware dispatches workgroup b to XCD b % 8; give
@@ -128,8 +123,11 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
         s_lo[tid] = INT_MAX;
         s_hi[tid] = INT_MIN;
     }
-    if (tid < RW) tqx[tid] = (double)min(max(x0 - RX + tid, 0), a.w - 1) + 0.5;
-    if (tid < RH) tqy[tid] = (double)min(max(y0 - RY + tid, 0), a.h - 1) + 0.5;
+    for (int s2 = tid; s2 < NS; s2 += NT) {
+        const int rx = s2 % RW, ry = s2 / RW;
+        tq[s2] = make_float2((float)min(max(x0 - RX + rx, 0), a.w - 1) + 0.5f,
+                             (float)min(max(y0 - RY + ry, 0), a.h - 1) + 0.5f);
+    }
     __syncthreads();
 
     uint32_t ref_hi[RPT], ref_lo[RPT];   // census cost: the reference census words
@@ -228,7 +226,7 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
                 const double h0 = Hm[0], h1 = Hm[1], h2 = Hm[2], h3 = Hm[3], h4 = Hm[4], h5 = Hm[5], h6 = Hm[6],
                              h7 = Hm[7], h8 = Hm[8];
                 const uint8_t *src = a.views[k];
-                warp_region<RW, NS>(buf, src, a.w, a.h, tqx, tqy, tid, h0, h1, h2, h3, h4, h5, h6, h7, h8);
+                warp_region<NS>(buf, src, a.w, a.h, tq, tid, h0, h1, h2, h3, h4, h5, h6, h7, h8);
             }
             __syncthreads();
             const bool left = a.side[k] < 0;
