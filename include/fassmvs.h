@@ -247,6 +247,15 @@ fassmvs_status fassmvs_filter_geometric(fassmvs_handle *h, int32_t w, int32_t hg
 /* ---------------------------------------------------------------------
  * Served form (online mapping from several UAV streams).
  *
+ * The online use the paper discusses with its run-times (Sec. on the
+ * discussion of run-time and online processing): one moving camera per
+ * sequence, frames used only with an appropriate baseline between them,
+ * and a new estimate for every new usable frame that reuses the images of
+ * the previous bundle.  Here the bundle is the frame and its stream's
+ * previous keyframes (a one-sided bundle; the paper takes the middle image
+ * of a bundle as reference, which would delay every estimate by half a
+ * bundle).
+ *
  * Frames of several streams are submitted as they arrive; each is matched
  * against its stream's previous keyframes (up to max_keyframes, all before
  * it in the sequence: a one-sided bundle, m = number of keyframes; a frame
