@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--served-slots", type=int, default=4)
     ap.add_argument("--served-frames", type=int, default=6, help="rendered frames per stream")
     ap.add_argument("--served-repeats", type=int, default=5, help="passes over each stream's frames")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time the sixteen uneven config4 frames one at a time and all in flight")
+    ap.add_argument("--batch-repeats", type=int, default=3)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device once (a plain copy kernel of known "
                          "size whose HBM byte counters calibrate the profiler's FETCH_SIZE / WRITE_SIZE)")
@@ -84,6 +87,10 @@ def main():
     if not args.no_served:
         served_streams = [scenegen.served_stream(seed, w, h, args.served_frames)
                           for seed, w, h in scenegen.SERVED_STREAMS]
+
+    batch_frames = None
+    if args.batch:
+        batch_frames = [scenegen.make_workload(f"config4_{sd}") for sd in scenegen.CONFIG4_SEEDS]
 
     wl = scenegen.make_workload(args.workload)
     cfg = fm.config_from_params(wl["params"], profile=1)
@@ -196,6 +203,8 @@ def main():
     }
     if served_streams is not None:
         out["served"] = served_bench(fm, served_streams, args.served_slots, args.served_repeats)
+    if batch_frames is not None:
+        out["batch"] = batch_bench(fm, batch_frames, args.batch_repeats)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out))
@@ -287,6 +296,57 @@ def served_bench(fm, streams, n_slots, repeats):
                          "x2": _run_trace(fm, srv, streams, events, 2.0),
                          "saturated": _run_trace(fm, srv, streams, events, 0)}
     return out
+
+
+def batch_bench(fm, frames, repeats):
+    """The sixteen uneven frames (config4 shapes), inputs in HBM, one handle
+    each (buffers allocated by an untimed first pass): one frame at a time
+    (submit, wait, next) against all sixteen submitted at once and then
+    collected.  Best of `repeats` passes each."""
+    hyp = 0.0
+    for wl in frames:
+        D, L = wl["families"][0]["count"], wl["params"]["n_levels"]
+        hyp += sum((wl["width"] >> l) * (wl["height"] >> l) * D for l in range(L))
+    handles = [fm.Handle(fm.config_from_params(wl["params"])) for wl in frames]
+    try:
+        inputs = []
+        for h, wl in zip(handles, frames):
+            ref = dict(wl["ref"], img=h.upload(wl["ref"]["img"]))
+            views = [dict(v, img=h.upload(v["img"])) for v in wl["views"]]
+            hh, ww = wl["height"], wl["width"]
+            outs = (h.empty((hh, ww), np.float32), h.empty((hh, ww, 3), np.float32), h.empty((hh, ww), np.float32))
+            inputs.append((ref, views, outs))
+
+        def submit(i):
+            ref, views, _ = inputs[i]
+            wl = frames[i]
+            return handles[i].submit_frame(ref, views, wl["side"], wl["K"], wl["families"], mem_kind=fm.MEM_DEVICE)
+
+        def wait(i, t):
+            d, n, c = inputs[i][2]
+            handles[i].poll(t, d, n, c, mem_kind=fm.MEM_DEVICE)
+
+        for i in range(len(frames)):   # allocations
+            wait(i, submit(i))
+        best_seq = best_all = float("inf")
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            for i in range(len(frames)):
+                wait(i, submit(i))
+            best_seq = min(best_seq, time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            tickets = [submit(i) for i in range(len(frames))]
+            for i, t in enumerate(tickets):
+                wait(i, t)
+            best_all = min(best_all, time.perf_counter() - t0)
+    finally:
+        for h in handles:
+            h.close()
+    res = {"frames": len(frames), "pixel_hyp": hyp}
+    for name, t in (("one_at_a_time", best_seq), ("all_in_flight", best_all)):
+        res[name] = {"ms": round(t * 1e3, 2), "frames_per_s": round(len(frames) / t, 1),
+                     "mpx_hyp_per_s": round(hyp / 1e6 / t, 1)}
+    return res
 
 
 def cpu_baseline(wl):
