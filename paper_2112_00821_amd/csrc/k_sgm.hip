@@ -48,7 +48,9 @@ __device__ __forceinline__ PathGeom path_geom(int dir, int pi, int w, int h) {
         g.len = h;
     } else {
         if (pi < w) {
-            g.sx = pi;
+            // longest paths first within each direction (the dispatcher
+            // starts workgroups in index order, so short paths fill the tail)
+            g.sx = g.dx > 0 ? pi : w - 1 - pi;
             g.sy = g.dy > 0 ? 0 : h - 1;
         } else {
             int j = pi - w;
