@@ -49,6 +49,7 @@ WORKLOADS = {
     "config1": "160x120 reference + 2 views, 32 planes, census 5x5, 8-path SGM P1=8 P2=64, 1 level",
     "config2_ncc": ("the 1920x1080 workload above matched with the negated, truncated, scaled NCC 5x5 "
                     "(phi1 = 100, adaptive P2)"),
+    "config2_pg": "the 1920x1080 workload above with SGM^Pi-pg (path-gradient index jump) at every level",
 }
 
 

@@ -576,6 +576,7 @@ WORKLOADS = {
     "config1_ncc": lambda: with_ncc(config1(0), p2_fixed=400),
     "config2_small_ncc": lambda: with_ncc(config2(1, 320, 184, planes=32, window=32)),
     "config2_ncc": lambda: with_ncc(config2(1)),
+    "config2_pg": lambda: with_sgm_variant(config2(1), 2),
     # plane counts from the cross-ratio construction (count 0)
     **{f"config4_{sd}": (lambda sd=sd: config4_frame(sd)) for sd in CONFIG4_SEEDS},
     "config1_xr": lambda: with_cross_ratio_counts(config1(0)),
@@ -606,6 +607,12 @@ def with_cross_ratio_counts(wl):
     """The same bundle with every family's coarsest plane count left to the
     cross-ratio construction (count 0)."""
     return dict(wl, families=[dict(f, count=0) for f in wl["families"]])
+
+
+def with_sgm_variant(wl, variant: int):
+    """The same bundle with another SGM smoothness term (0 Pi, 1 Pi-sn,
+    2 Pi-pg)."""
+    return dict(wl, params=dict(wl["params"], sgm_variant=variant))
 
 
 def with_ncc(wl, window: int = 5, p1: int = 100, p2_fixed: int | None = None):
