@@ -312,14 +312,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *p, int by
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
 }
 
-template <int KP, int NF, bool WIN, bool SN>
+template <int KP, int NF, bool WIN, bool SN, bool PG>
 __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
     constexpr int PF = 16;
     constexpr int G2 = 6;
     constexpr int LW = (kMaxLabels + 2 * G2 * kMaxFam) / 2 + 1;   // 32-bit words per buffer, last one a sink
     __shared__ uint32_t lbuf[WAVES][2][LW];
     __shared__ int s_lut[256];   // P2 by intensity change
+    __shared__ double pdelta[PG ? kMaxPgPlanes : 1];   // path gradient: the level's plane lists
     for (int i = threadIdx.x; i < 256; i += 64 * WAVES) s_lut[i] = a.lut[i];
+    if (PG)
+        for (int i = threadIdx.x; i < a.sumG; i += 64 * WAVES) pdelta[i] = a.delta[i];
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -424,6 +427,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
     int oq[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) oq[f] = 0;
+    // path-gradient state: depths of the last two minimum-cost points, 2/d
+    // of each, and -n^T K^-1 p of the previous pixel per family.  Values
+    // carried from one step to the next are the same doubles the formulas
+    // would recompute (the ray and its dot products of a pixel, and
+    // 1/d = (2/d) / 2, exact in binary floating point).
+    double dq1 = 0.0, dq2 = 0.0, a1 = 0.0, a2 = 0.0;
+    double c_prev[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) c_prev[f] = 0.0;
 
     // Row pointers advance by one path step at a time (two scalar adds)
     // instead of being recomputed from the step index: s_ahead is the cost
@@ -464,6 +476,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
         for (int f = 0; f < NF; ++f) op[f] = WIN ? __builtin_amdgcn_readlane(c_off[f], u) : 0;
         uint32_t *cur = (u & 1) ? buf1 : buf0;
         const uint32_t *prev = (u & 1) ? buf0 : buf1;
+        double c_cur[NF];   // path gradient: -n^T K^-1 p of this step's pixel
         {
             // splats of uniform 16-bit values (the packed instructions take
             // them as one scalar operand)
@@ -478,6 +491,34 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
                 int v = WIN ? op[f] - oq[f] : 0;
                 if (SN) v += __builtin_amdgcn_readlane(c_di[f], u);
                 sh[f] = v;
+            }
+            // -n^T K^-1 p of this step's pixel per family (path gradient)
+            if (PG) {
+                const int px = pg.sx + t * pg.dx, py = pg.sy + t * pg.dy;
+                double rp[3];
+                ray_of(a.Kinv, px + 0.5, py + 0.5, rp);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const double *n = a.fam_n[f < F ? f : 0];
+                    c_cur[f] = -(n[0] * rp[0] + n[1] * rp[1] + n[2] * rp[2]);
+                }
+            }
+            if (PG && t >= 2 && dq1 > 0.0 && dq2 > 0.0) {
+                // extrapolated inverse depth of the path's minimum-cost
+                // points, as a plane-index jump per family:
+                // 1/d* = 2/dq1 - 1/dq2
+                const double inv = a1 - 0.5 * a2;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    if (f >= F) break;
+                    const double cp = c_cur[f], cq = c_prev[f];
+                    if (!(cp > 0.0) || !(cq > 0.0)) continue;
+                    const double ip = inv / cp;
+                    const double iq = 1.0 / (dq1 * cq);
+                    double v = (ip - iq) / a.step[f];
+                    v = fmin(fmax(v, -7.0), 7.0);
+                    sh[f] += (int)round(v);
+                }
             }
 #pragma unroll
             for (int k = 0; k < KP; ++k) {
@@ -524,9 +565,40 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
             m2 = __builtin_elementwise_min(m2, (all_valid || lv[k]) ? L[k] : as_u16x2(0xFFFFFFFFu));
         }
         __builtin_amdgcn_wave_barrier();
-        const uint32_t mw = as_u32(m2);
-        const uint32_t lo = mw & 0xFFFFu, hi = mw >> 16;
-        Mq = wave_min_u32(lo < hi ? lo : hi);
+        if (PG) {
+            // minimum and its label in one reduction (smallest label on ties)
+            uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                const uint32_t lw = as_u32(L[k]);
+                const uint32_t i0 = lo8[k];
+                const uint32_t k0 = (lw << 16) | i0, k1 = (lw & 0xFFFF0000u) | (i0 + 1);
+                const bool ok = all_valid || lv[k];
+                key = ok && k0 < key ? k0 : key;
+                key = ok && k1 < key ? k1 : key;
+            }
+            key = wave_min_u32(key);
+            Mq = key >> 16;
+            const int bi = (int)(key & 0xFFFFu);
+            int f = 0;
+            while (f + 1 < F && bi >= a.foff[f + 1]) ++f;
+            const int g = (WIN ? op[f] : 0) + (bi - a.foff[f]);
+            double cf = c_cur[0];
+#pragma unroll
+            for (int ff = 1; ff < NF; ++ff)
+                if (ff == f) cf = c_cur[ff];
+            const double den = -cf;   // n^T K^-1 p, exactly
+            dq2 = dq1;
+            a2 = a1;
+            dq1 = den < 0.0 ? -pdelta[a.goff[f] + g] / den : 0.0;
+            a1 = dq1 > 0.0 ? 2.0 / dq1 : 0.0;
+#pragma unroll
+            for (int ff = 0; ff < NF; ++ff) c_prev[ff] = c_cur[ff];
+        } else {
+            const uint32_t mw = as_u32(m2);
+            const uint32_t lo = mw & 0xFFFFu, hi = mw >> 16;
+            Mq = wave_min_u32(lo < hi ? lo : hi);
+        }
 #pragma unroll
         for (int f = 0; f < NF; ++f) oq[f] = op[f];
     };
@@ -746,25 +818,27 @@ static void launch_k(const SgmArgs &a, bool win, bool sn, dim3 grid, hipStream_t
 
 template <int KP>
 static void launch_pk(const SgmArgs &a, bool win, bool sn, dim3 grid, hipStream_t s) {
-#define FMVS_SGMPK(W_, S_)                                                                    \
-    if (win == W_ && sn == S_) {                                                              \
-        if (a.n_fam == 1)                                                                     \
-            hipLaunchKernelGGL((k_sgm_pk<KP, 1, W_, S_>), grid, dim3(64 * WAVES), 0, s, a);   \
-        else                                                                                  \
-            hipLaunchKernelGGL((k_sgm_pk<KP, kMaxFam, W_, S_>), grid, dim3(64 * WAVES), 0, s, a); \
-        return;                                                                               \
+#define FMVS_SGMPK(W_, S_, P_)                                                                     \
+    if (win == W_ && sn == S_ && (a.pg != 0) == P_) {                                              \
+        if (a.n_fam == 1)                                                                          \
+            hipLaunchKernelGGL((k_sgm_pk<KP, 1, W_, S_, P_>), grid, dim3(64 * WAVES), 0, s, a);    \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_sgm_pk<KP, kMaxFam, W_, S_, P_>), grid, dim3(64 * WAVES), 0, s, a); \
+        return;                                                                                    \
     }
-    FMVS_SGMPK(false, false)
-    FMVS_SGMPK(true, false)
-    FMVS_SGMPK(false, true)
-    FMVS_SGMPK(true, true)
+    FMVS_SGMPK(false, false, false)
+    FMVS_SGMPK(true, false, false)
+    FMVS_SGMPK(false, true, false)
+    FMVS_SGMPK(true, true, false)
+    FMVS_SGMPK(false, false, true)
+    FMVS_SGMPK(true, false, true)
 #undef FMVS_SGMPK
 }
 
-// Packed two-label kernel when every family window is even and the
-// path-gradient variant is off; the one-label kernel otherwise.
+// Packed two-label kernel when every family window is even (all variants);
+// the one-label kernel otherwise.
 static bool use_packed(const SgmArgs &a) {
-    if (a.final_mode || a.pg || (a.D & 1)) return false;
+    if (a.final_mode || (a.D & 1)) return false;
     for (int f = 0; f < a.n_fam; ++f)
         if (a.W[f] & 1) return false;
     // FASSMVS_SGM_UNPACKED=1 selects the one-label kernel (same results);
