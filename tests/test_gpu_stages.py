@@ -235,10 +235,13 @@ def test_seed_bit_exact(orc, hd):
     assert np.mean(dI.numpy() == seed["dI"]) >= 0.9999
 
 
+@pytest.mark.parametrize("kernel", ["packed", "one-label"])
 @pytest.mark.parametrize("name,level", [("config2_small", 1), ("config3_small", 1), ("config1", 0)])
-def test_sgm_path_gradient_bit_exact(orc, hd, name, level):
+def test_sgm_path_gradient_bit_exact(orc, hd, monkeypatch, kernel, name, level):
     """SGM^Pi-pg: path costs and aggregate bit-exact with the oracle's
-    path-gradient recursion (windows and plane families included)."""
+    path-gradient recursion (windows and plane families included), through
+    the two-label and the one-label kernel."""
+    monkeypatch.setenv("FASSMVS_SGM_UNPACKED", "1" if kernel == "one-label" else "0")
     wl = scenegen.make_workload(name)
     out = orc.run_frame(wl, keep=True, levels_only=level)
     lv = out["levels"][level]
