@@ -65,7 +65,7 @@ def main():
                          "that PCIe-inclusive rate beside the device-resident one")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served-vs-plain measurement on the four-stream trace")
-    ap.add_argument("--served-slots", type=int, default=4)
+    ap.add_argument("--served-slots", type=int, default=3)
     ap.add_argument("--served-frames", type=int, default=6, help="rendered frames per stream")
     ap.add_argument("--served-repeats", type=int, default=5, help="passes over each stream's frames")
     ap.add_argument("--batch", action="store_true",
