@@ -363,7 +363,16 @@ def cpu_baseline(wl):
     hh, ww = lv["depth"].shape
     plan = oracle.level_plan(wl, top)
     hyp = hh * ww * sum(plan["W"])
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(hyp / 1e6 / el, 3), "unit": "Mpx·hyp/s", "cores": 1, "kind": "oracle",
+            "host_cpu": cpu, "host_threads_visible": os.cpu_count(),
             "sample": f"coarsest level of the same frame ({ww}x{hh} x {sum(plan['W'])} planes, pyramid + "
                       f"census + cost volume + 8-path SGM + refinement + median + normals + confidence), "
                       f"{el:.1f} s single-threaded"}
