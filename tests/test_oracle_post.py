@@ -83,6 +83,33 @@ def test_normal_smoothing_weights(orc):
     assert ratio == pytest.approx(w_q, rel=1e-5)
 
 
+@pytest.mark.parametrize("radius", [1, 2, 3])
+def test_normal_smoothing_on_flat_intensity_is_a_gaussian_correlation(orc, radius):
+    """With one intensity everywhere the appearance term is 1 and Eq.
+    normal-smooth becomes a correlation of the normal field with the
+    Gaussian of sigma = radius over the (2r+1)^2 window, the pixel itself
+    taken with weight 1 and neighbours outside the image left out: checked
+    against scipy's correlate, then normalised."""
+    from scipy import ndimage
+    rng = np.random.default_rng(radius)
+    h, w = 17, 23
+    f = rng.normal(0, 1, (h, w, 3)).astype(np.float32)
+    f[..., 2] = -np.abs(f[..., 2]) - 0.5
+    f /= np.linalg.norm(f, axis=-1, keepdims=True)
+    f[rng.random((h, w)) < 0.1] = 0.0          # invalid normals take no part
+    img = np.full((h, w), 77, np.uint8)
+    sig = float(radius)
+    yy, xx = np.mgrid[-radius:radius + 1, -radius:radius + 1]
+    ker = np.exp(-(xx ** 2 + yy ** 2) / (2 * sig * sig)) / math.sqrt(2 * math.pi * sig * sig)
+    ker[radius, radius] = 1.0
+    acc = np.stack([ndimage.correlate(f[..., c].astype(np.float64), ker, mode="constant", cval=0.0)
+                    for c in range(3)], axis=-1)
+    valid = np.any(f != 0, axis=-1)
+    exp = np.where(valid[..., None], acc / np.linalg.norm(acc, axis=-1, keepdims=True), 0.0)
+    got = orc.normal_smooth(f, img, radius, 10.0)
+    assert np.max(np.abs(got - exp)) < 2e-6
+
+
 def test_confidence_closed_forms(orc):
     fam_n = np.array([[0, 0, -1.0]])
     lab = np.zeros((1, 4), np.int32)
