@@ -7,10 +7,10 @@ module binds them with ctypes and drives one frame coarse-to-fine
 (pipeline overview of the paper's methodology section).  It shares no code
 with the GPU library.
 
-Parity status: pinned by the CPU tests (closed forms, brute force,
-invariants, ground-truth recovery); normal smoothing and confidence are
-pinned only on their closed-form special cases ("parity unpinned" beyond
-those, tolerance derived from float arithmetic).
+Parity status: pinned by the CPU tests (closed forms, brute force, library
+routines on special cases, invariants, ground-truth recovery); the normal
+smoothing through fixed points, a two-pixel weight ratio and, on flat
+intensity, a Gaussian correlation; the confidence through closed forms.
 """
 from __future__ import annotations
 

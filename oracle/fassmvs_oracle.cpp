@@ -24,9 +24,10 @@
 //    skipped) lands in bit (nbits-1-b); bit = [W(q) < W(p)] (strict).
 //
 // Parity status: every function here is pinned by the CPU test-suite
-// (closed forms, brute force, invariants, ground-truth recovery), except the
-// normal smoothing weights and the confidence value beyond its closed-form
-// special cases, whose tolerance is derived from float arithmetic.
+// (closed forms, brute force, library routines on special cases,
+// invariants, ground-truth recovery); the normal smoothing through its
+// fixed points, a two-pixel weight ratio and, on flat intensity, a Gaussian
+// correlation; the confidence through closed forms.
 
 #include <algorithm>
 #include <cmath>
