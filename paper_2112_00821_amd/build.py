@@ -15,6 +15,9 @@ SOURCES = ["k_image.hip", "k_sweep.hip", "k_sgm.hip", "k_post.hip", "runtime.hip
 # sweep variants (window width, height, cost: 0 census, 1 NCC), one object
 # each from k_sweep_inst.hip so they compile in parallel
 SWEEP_VARIANTS = [(5, 5, 0), (9, 7, 0), (7, 7, 0), (3, 3, 0), (5, 5, 1), (9, 9, 1), (7, 7, 1), (3, 3, 1)]
+# two-label SGM kernels by label pairs per lane, one object each from
+# k_sgm_inst.hip
+SGM_PAIRS = [1, 2, 3, 4]
 ARCH = os.environ.get("FASSMVS_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -35,6 +38,8 @@ def _units():
     for cw, ch, cost in SWEEP_VARIANTS:
         units.append(("k_sweep_inst.hip", f"k_sweep_{cw}x{ch}_{cost}",
                       [f"-DFMVS_CW={cw}", f"-DFMVS_CH={ch}", f"-DFMVS_COST={cost}"]))
+    for kp in SGM_PAIRS:
+        units.append(("k_sgm_inst.hip", f"k_sgm_pk{kp}", [f"-DFMVS_KP={kp}"]))
     return units
 
 
@@ -52,7 +57,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     units = _units()
     # heaviest first: the sweep variants and the SGM dominate the build
-    order = sorted(units, key=lambda u: (u[0] not in ("k_sweep_inst.hip", "k_sgm.hip"), u[1]))
+    order = sorted(units, key=lambda u: (u[0] not in ("k_sgm_inst.hip", "k_sweep_inst.hip", "k_sgm.hip"), u[1]))
     with ThreadPoolExecutor(max_workers=min(len(order), os.cpu_count() or 8)) as ex:
         objs = list(ex.map(_compile, order))
     tmp = LIB + ".tmp"

@@ -27,9 +27,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # once any of them changes)
 KERNEL_SOURCES = {
     "k_sweep": ["csrc/k_sweep.hpp", "csrc/k_sweep.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
-    "k_sgm": ["csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
-    "k_sgm_pk": ["csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
-    "k_wta16": ["csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
+    "k_sgm": ["csrc/k_sgm.hpp", "csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
+    "k_sgm_pk": ["csrc/k_sgm.hpp", "csrc/k_sgm_inst.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
+    "k_wta16": ["csrc/k_sgm.hpp", "csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
 }
 
 
