@@ -50,6 +50,8 @@ WORKLOADS = {
     "config2_ncc": ("the 1920x1080 workload above matched with the negated, truncated, scaled NCC 5x5 "
                     "(phi1 = 100, adaptive P2)"),
     "config2_pg": "the 1920x1080 workload above with SGM^Pi-pg (path-gradient index jump) at every level",
+    "config3": ("2704x1520 reference + 4 views of the same scene generator, 4 plane families (fronto, ground "
+                "normal, ground normal tilted +-20 deg) x 96 planes per level, 3 levels, census 9x7, SGM^Pi-sn"),
 }
 
 
@@ -65,7 +67,7 @@ def main():
                          "that PCIe-inclusive rate beside the device-resident one")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served-vs-plain measurement on the four-stream trace")
-    ap.add_argument("--served-slots", type=int, default=3)
+    ap.add_argument("--served-slots", type=int, default=2)
     ap.add_argument("--served-frames", type=int, default=6, help="rendered frames per stream")
     ap.add_argument("--served-repeats", type=int, default=5, help="passes over each stream's frames")
     ap.add_argument("--batch", action="store_true",
