@@ -632,6 +632,8 @@ void sgm_launch_pk(const SgmArgs &a, bool win, bool sn, dim3 grid, hipStream_t s
     if (win == W_ && sn == S_ && (a.pg != 0) == P_) {                                              \
         if (a.n_fam == 1)                                                                          \
             hipLaunchKernelGGL((k_sgm_pk<KP, 1, W_, S_, P_>), grid, dim3(64 * WAVES), 0, s, a);    \
+        else if (a.n_fam <= 4)                                                                     \
+            hipLaunchKernelGGL((k_sgm_pk<KP, 4, W_, S_, P_>), grid, dim3(64 * WAVES), 0, s, a);    \
         else                                                                                       \
             hipLaunchKernelGGL((k_sgm_pk<KP, kMaxFam, W_, S_, P_>), grid, dim3(64 * WAVES), 0, s, a); \
         return;                                                                                    \
