@@ -1,12 +1,16 @@
 /*
  * fassmvs.h -- C ABI of the MI355X (gfx950) implementation of the FaSS-MVS
  * hot path: hierarchical plane-sweep multi-image matching with a
- * census-Hamming cost (Alg. 1 of the paper; Eq. homography) followed by
- * surface-aware semi-global matching (Eq. sgm-path ... sgm-smooth-sn,
- * Eq. p2-grad), winner-takes-all plane selection with sub-plane depth
- * refinement, normal map (Eq. normal, normal-smooth) and geometric
- * confidence (Eq. weight-normal), run coarse-to-fine over a Gaussian
- * pyramid (pipeline overview; Eq. sampling_range).
+ * census-Hamming or NCC cost (Alg. 1 of the paper; Eq. homography) followed
+ * by surface-aware semi-global matching (Eq. sgm-path ... sgm-smooth-sn,
+ * sgm-smooth-pg, Eq. p2-grad), winner-takes-all plane selection with
+ * sub-plane depth refinement, normal map (Eq. normal, normal-smooth) and
+ * geometric confidence (Eq. weight-normal), run coarse-to-fine over a
+ * Gaussian pyramid (pipeline overview; Eq. sampling_range).  Around it: the
+ * plane-set generator (bounding planes, cross-ratio steps of Alg. 2), the
+ * post-filters (DoG texture mask, Alg. 3; geometric consistency, Alg. 4),
+ * per-stage entry points on caller-owned device buffers, and a served form
+ * for several concurrent UAV streams.
  *
  * The library is self-contained: plain C types, no exceptions cross the
  * boundary, every call returns a status.  Device memory is owned by the
