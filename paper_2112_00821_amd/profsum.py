@@ -23,13 +23,15 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# sources each timed kernel is built from (the hash marks the counters stale
-# once any of them changes)
+# sources each timed kernel is built from, and the build script that holds
+# its compiler flags (the hash marks the counters stale once any of them
+# changes)
 KERNEL_SOURCES = {
-    "k_sweep": ["csrc/k_sweep.hpp", "csrc/k_sweep.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
-    "k_sgm": ["csrc/k_sgm.hpp", "csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
-    "k_sgm_pk": ["csrc/k_sgm.hpp", "csrc/k_sgm_inst.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
-    "k_wta16": ["csrc/k_sgm.hpp", "csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp"],
+    "k_sweep": ["csrc/k_sweep.hpp", "csrc/k_sweep.hip", "csrc/k_sweep_inst.hip", "csrc/dev_common.hpp",
+                "csrc/kernels.hpp", "build.py"],
+    "k_sgm": ["csrc/k_sgm.hpp", "csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp", "build.py"],
+    "k_sgm_pk": ["csrc/k_sgm.hpp", "csrc/k_sgm_inst.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp", "build.py"],
+    "k_wta16": ["csrc/k_sgm.hpp", "csrc/k_sgm.hip", "csrc/dev_common.hpp", "csrc/kernels.hpp", "build.py"],
 }
 
 
