@@ -207,9 +207,12 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
 
     int it = 0;
     for (int pos = pos0; pos < pos1; ++pos) {
-        int sL[RPT], sR[RPT];
+        // left-view sums in the low 16 bits, right-view sums in the high 16
+        // (at most 8 views of at most 255 each): one shift-add per view and
+        // pixel, the subset decided by a uniform shift
+        uint32_t sLR[RPT];
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) sL[j] = sR[j] = 0;
+        for (int j = 0; j < RPT; ++j) sLR[j] = 0;
         const size_t lab = (size_t)a.goff[f] + g;
         for (int k = 0; k < a.n_views; ++k, ++it) {
             float *buf = wbuf[it & 1];
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
                 warp_region<NS>(buf, src, a.w, a.h, tq, tid, h0, h1, h2, h3, h4, h5, h6, h7, h8);
             }
             __syncthreads();
-            const bool left = a.side[k] < 0;
+            const uint32_t sh = a.side[k] < 0 ? 0u : 16u;
             const float *base = buf + (ty * RPT) * RW + tx;
             if (COST == 0) {
                 // census of the warped view for this thread's pixels
@@ -261,8 +264,8 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
                 }
 #pragma unroll
                 for (int j = 0; j < RPT; ++j) {
-                    int cst = __popc(hi[j] ^ ref_hi[j]) + __popc(lo[j] ^ ref_lo[j]);
-                    if (left) sL[j] += cst; else sR[j] += cst;
+                    const uint32_t cst = __popc(hi[j] ^ ref_hi[j]) + __popc(lo[j] ^ ref_lo[j]);
+                    sLR[j] += cst << sh;
                 }
             } else {
                 // NCC: row sums of the window rows, left to right, then the
@@ -298,8 +301,8 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
                 }
 #pragma unroll
                 for (int j = 0; j < RPT; ++j) {
-                    const int cst = ncc_finish(refA[j], refV[j], wB[j], wBB[j], wAB[j], (double)(CW * CH));
-                    if (left) sL[j] += cst; else sR[j] += cst;
+                    const uint32_t cst = (uint32_t)ncc_finish(refA[j], refV[j], wB[j], wBB[j], wAB[j], (double)(CW * CH));
+                    sLR[j] += cst << sh;
                 }
             }
         }
@@ -308,8 +311,9 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
         for (int j = 0; j < RPT; ++j) {
             const int o = off[j];
             if (valid[j] && g >= o && g < o + a.W[f]) {
-                const uint32_t cst = COST == 0 ? (uint32_t)combine_lr(sL[j], sR[j], a.nL, a.nR, a.m)
-                                               : (uint32_t)combine_mean(sL[j], sR[j], a.nL, a.nR);
+                const int sL = (int)(sLR[j] & 0xFFFFu), sR = (int)(sLR[j] >> 16);
+                const uint32_t cst = COST == 0 ? (uint32_t)combine_lr(sL, sR, a.nL, a.nR, a.m)
+                                               : (uint32_t)combine_mean(sL, sR, a.nL, a.nR);
                 const int idx = a.foff[f] + (g - o);
                 uint8_t *dst = a.S + (size_t)pix[j] * a.D + idx;
                 if (pack) {
