@@ -144,8 +144,7 @@ def test_coarsest_level(orc, run):
     xy = np.concatenate([xy, [[0, 0], [ww - 1, hh - 1], [ww - 1, 0], [0, hh - 1]]]).astype(np.int32)
     exp = _cost_pixels(orc, wl, img, views, plan, H, xy)
     got = S[xy[:, 1], xy[:, 0]]
-    assert np.mean(got == exp) >= 0.9999
-    assert np.max(np.abs(got.astype(int) - exp.astype(int))) <= 2
+    assert np.array_equal(got, exp), np.mean(got == exp)
 
 
 def test_level0_windows_centred_on_seed(orc, run):
@@ -172,6 +171,8 @@ def test_level0_cost_samples(orc, run):
     xy = np.concatenate([xy, [[0, 0], [ww - 1, hh - 1], [ww - 1, 0], [0, hh - 1]]])
     exp = _cost_pixels(orc, wl, wl["ref"]["img"], [v["img"] for v in wl["views"]], plan, H, xy, offs=offs)
     got = S[xy[:, 1], xy[:, 0]]
+    # the pipeline's own homographies (computed apart from the oracle's) may
+    # differ in the last bit, which can flip a census bit of a rare sample
     assert np.mean(got == exp) >= 0.9999
     assert np.max(np.abs(got.astype(int) - exp.astype(int))) <= 2
 
