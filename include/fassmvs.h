@@ -105,13 +105,28 @@ typedef struct {
 
 typedef struct {
     double n[3];               /* unit normal in reference-camera coordinates, n[2] < 0 */
-    double delta_min;          /* nearest plane distance, > 0 */
+    double delta_min;          /* nearest plane distance, > 0; with delta_max 0 and delta NULL:
+                                  taken from the depth range (see depth_min) */
     double delta_max;          /* farthest plane distance, > delta_min */
-    int32_t count;             /* planes at the coarsest level (2..256); level l uses
-                                  count * 2^(n-1-l) planes uniform in 1/delta.  0: as many
-                                  as the cross-ratio construction yields at the coarsest
-                                  level for the view with the longest epipolar segment
-                                  (fassmvs_cross_ratio_planes), capped at 256 */
+    int32_t count;             /* planes at the coarsest level (2..256), uniform in 1/delta over
+                                  [delta_min, delta_max]; with delta != NULL the length of that
+                                  list.  0 (and delta NULL): the cross-ratio list (Alg. 2,
+                                  fassmvs_cross_ratio_planes) at the coarsest level for the view
+                                  with the longest epipolar segment, resampled to 256 planes
+                                  when longer */
+    const double *delta;       /* NULL, or the coarsest level's plane distances (host memory,
+                                  count entries, > 0, strictly increasing or strictly decreasing;
+                                  copied before the call returns): the paper's set of planes
+                                  with varying distances (Alg. 1) */
+    double depth_min;          /* depth range [depth_min, depth_max] of the reference view; when */
+    double depth_max;          /* delta_min = delta_max = 0 and delta is NULL, the family's
+                                  bounding planes (fassmvs_bounding_planes) give its range */
+    /* Level l uses count * 2^(n-1-l) planes: the inverse distance is
+     * interpolated linearly at the fractional indices j (count - 1) /
+     * (G_l - 1) of the coarsest list (a list uniform in 1/delta stays
+     * uniform).  The coarse-to-fine windows and the surface-normal offsets
+     * index the level's list by the continuous index of an inverse distance
+     * (piecewise linear between planes).  SGM^Pi-pg needs uniform lists. */
 } fassmvs_plane_family;
 
 /* Paper defaults: 8 paths, SGM^Pi, census 9x7, P1 24 (census 9x7 setting of
@@ -267,9 +282,11 @@ fassmvs_status fassmvs_filter_geometric(fassmvs_handle *h, int32_t w, int32_t hg
  * since the last keyframe, the first frame always does), so the stream's
  * keyframe images stay on the device.  A worker thread admits queued frames
  * in arrival order into n_slots pipeline slots (each a handle with its own
- * HIP stream, so admitted frames run concurrently) while the sum of the
- * admitted frames' footprints (fassmvs_frame_footprint) stays within the
- * budget, and collects finished frames into result maps on the device.
+ * HIP stream, so admitted frames run concurrently) while the device memory
+ * the slots hold plus the growth the frame needs on its slot stays within
+ * the budget (a slot's buffers grow only while no frame is in flight; idle
+ * slots release theirs when the budget is short), and collects finished
+ * frames into result maps on the device.
  * Results are the same as the plain pipeline's on the same bundle.
  * --------------------------------------------------------------------- */
 typedef struct fassmvs_server fassmvs_server;
@@ -452,13 +469,17 @@ fassmvs_status fassmvs_stage_normals(fassmvs_handle *h, const float *depth, cons
 /* Coarse-to-fine seeds (pipeline overview; dynamic cost volume;
  * Eq. sgm-smooth-sn): nearest-neighbour upsampling of the coarse depth and
  * normal (cw x ch) to the fine level (fw x fh), the per-family sampling
- * windows and, when dI != NULL, the surface-normal index offsets for the 8
- * path directions.  Kinv: fine level; inv_dmin, step, G, W per family. */
+ * windows (W[f] planes centred on the rounded continuous index of the seed
+ * point's inverse distance in the family's list of the fine level) and,
+ * when dI != NULL, the surface-normal index offsets for the 8 path
+ * directions (difference of continuous indices, rounded half away from
+ * zero, clamped to +-7).  Kinv: fine level; host arrays fam_n [F][3],
+ * fam_delta (the fine level's lists of every family, concatenated,
+ * increasing distances), G, W per family. */
 fassmvs_status fassmvs_stage_seed(fassmvs_handle *h, const float *depth_c, const float *normal_c, int32_t cw,
                                   int32_t ch, int32_t fw, int32_t fh, const double *Kinv, int32_t n_fam,
-                                  const double *fam_n, const double *inv_dmin, const double *step,
-                                  const int32_t *G, const int32_t *W, float *dbar, float *nbar, int32_t *offs,
-                                  int8_t *dI);
+                                  const double *fam_n, const double *fam_delta, const int32_t *G, const int32_t *W,
+                                  float *dbar, float *nbar, int32_t *offs, int8_t *dI);
 
 #ifdef __cplusplus
 }

@@ -80,8 +80,10 @@ def _declare(L):
         "or_normal_smooth": (None, [vp, vp, i, i, i, d, vp]),
         "or_confidence": (None, [vp, vp, vp, vp, i, i, d, vp]),
         "or_upsample_nn": (None, [vp, i, i, i, i, i, vp]),
-        "or_window_offsets": (None, [vp, i, i, vp, i, vp, vp, vp, vp, vp, vp]),
-        "or_delta_i": (None, [vp, vp, i, i, vp, i, vp, vp, vp]),
+        "or_window_offsets": (None, [vp, i, i, vp, i, vp, vp, vp, vp, vp]),
+        "or_delta_i": (None, [vp, vp, i, i, vp, i, vp, vp, vp, vp]),
+        "or_level_list": (i, [vp, i, i, vp]),
+        "or_list_index": (d, [vp, i, d]),
         "or_gauss_taps": (None, [d, i, vp]),
         "or_dog": (None, [vp, i, i, d, i, vp]),
         "or_dog_mask": (None, [vp, i, i, d, i, d, i, i, vp]),
@@ -132,6 +134,24 @@ def plane_list(dmin, dmax, G):
     out = np.zeros(G)
     lib().or_plane_list(float(dmin), float(dmax), int(G), _p(out))
     return out
+
+
+def level_list(top, G):
+    """The G-plane list of a finer level from the coarsest list ``top``
+    (increasing distances): inverse distance interpolated at the fractional
+    indices j (len(top) - 1) / (G - 1)."""
+    top = _c(top, np.float64)
+    out = np.zeros(int(G))
+    if lib().or_level_list(_p(top), len(top), int(G), _p(out)) != 0:
+        raise ValueError("level_list: lists need at least two planes")
+    return out
+
+
+def list_index(deltas, inv_delta):
+    """Continuous index of an inverse distance in a plane list (piecewise
+    linear between the planes, end intervals extended)."""
+    d = _c(deltas, np.float64)
+    return lib().or_list_index(_p(d), len(d), float(inv_delta))
 
 
 def depth_on_plane(Kinv, n, delta, x, y):
@@ -342,24 +362,31 @@ def upsample_nn(src, dw, dh):
     return out
 
 
-def window_offsets(dbar, Kinv, fam_n, inv_dmin, step, G, W):
+def window_offsets(dbar, Kinv, fam_n, deltas, W):
+    """Per-pixel sampling windows; deltas: the level's plane list of every
+    family (a list of arrays)."""
     dbar = _c(dbar, np.float32)
     h, w = dbar.shape
-    nf = len(G)
+    nf = len(deltas)
+    G = np.array([len(d) for d in deltas], np.int32)
+    cat = _c(np.concatenate([np.asarray(d, np.float64) for d in deltas]), np.float64)
     offs = np.zeros((nf, h, w), np.int32)
-    lib().or_window_offsets(_p(dbar), w, h, _p(_c(Kinv, np.float64)), nf, _p(_c(fam_n, np.float64)),
-                            _p(_c(inv_dmin, np.float64)), _p(_c(step, np.float64)),
-                            _p(np.asarray(G, np.int32)), _p(np.asarray(W, np.int32)), _p(offs))
+    lib().or_window_offsets(_p(dbar), w, h, _p(_c(Kinv, np.float64)), nf, _p(_c(fam_n, np.float64)), _p(cat),
+                            _p(G), _p(np.asarray(W, np.int32)), _p(offs))
     return offs
 
 
-def delta_i(dbar, nbar, Kinv, fam_n, step):
+def delta_i(dbar, nbar, Kinv, fam_n, deltas):
+    """Surface-normal index offsets; deltas: the level's plane list of every
+    family."""
     dbar = _c(dbar, np.float32)
     h, w = dbar.shape
-    nf = len(step)
+    nf = len(deltas)
+    G = np.array([len(d) for d in deltas], np.int32)
+    cat = _c(np.concatenate([np.asarray(d, np.float64) for d in deltas]), np.float64)
     out = np.zeros((8, h, w, nf), np.int8)
     lib().or_delta_i(_p(dbar), _p(_c(nbar, np.float32)), w, h, _p(_c(Kinv, np.float64)), nf,
-                     _p(_c(fam_n, np.float64)), _p(_c(step, np.float64)), _p(out))
+                     _p(_c(fam_n, np.float64)), _p(cat), _p(G), _p(out))
     return out
 
 
@@ -367,41 +394,78 @@ def delta_i(dbar, nbar, Kinv, fam_n, step):
 # frame driver
 # ---------------------------------------------------------------------------
 
-def family_count(wl, fam):
-    """Planes of a family at the coarsest level; count 0 takes the length of
-    the cross-ratio list (coarsest-level intrinsics) of the view with the
-    longest one, capped at 256."""
+MAX_TOP_PLANES = 256
+
+
+def family_range(wl, fam):
+    """(delta_min, delta_max) of a family: given, or -- when both are 0 --
+    the bounding planes of the depth range [depth_min, depth_max] over the
+    reference frustum (level-0 intrinsics and size)."""
+    lo, hi = float(fam.get("delta_min", 0.0)), float(fam.get("delta_max", 0.0))
+    if lo == 0.0 and hi == 0.0:
+        return bounding_planes(np.asarray(wl["K"], np.float64), wl["width"], wl["height"], fam["n"],
+                               fam["depth_min"], fam["depth_max"])
+    return lo, hi
+
+
+def top_list(wl, fam):
+    """The coarsest level's plane list of a family, increasing distances:
+    the caller's explicit list ("delta", either order); count > 0: count
+    planes uniform in inverse distance over the family's range; count 0:
+    the cross-ratio list (Alg. 2, coarsest-level intrinsics and size) of
+    the view with the longest one, resampled to 256 planes when longer."""
+    if fam.get("delta") is not None:
+        d = np.asarray(fam["delta"], np.float64)
+        return d[::-1].copy() if d[0] > d[-1] else d.copy()
+    lo, hi = family_range(wl, fam)
     if int(fam["count"]) != 0:
-        return int(fam["count"])
+        return plane_list(lo, hi, int(fam["count"]))
     n = wl["params"]["n_levels"]
     _, Kt = kinv_level(np.asarray(wl["K"], np.float64), n - 1)
     wt, ht = wl["width"] >> (n - 1), wl["height"] >> (n - 1)
-    best = 0
+    best = None
     for v in wl["views"]:
         R, t = relative_pose(wl["ref"]["R"], wl["ref"]["t"], v["R"], v["t"])
         try:
-            best = max(best, len(cross_ratio_planes(Kt, wt, ht, R, t, fam["n"], fam["delta_min"], fam["delta_max"])))
+            lst = cross_ratio_planes(Kt, wt, ht, R, t, fam["n"], lo, hi)
         except ValueError:
-            pass
-    return min(best, 256)
+            continue
+        if best is None or len(lst) > len(best):
+            best = lst
+    if best is None or len(best) < 2:
+        raise ValueError("no cross-ratio plane list for a family with count 0")
+    best = best[::-1].copy()
+    if len(best) > MAX_TOP_PLANES:
+        best = level_list(best, MAX_TOP_PLANES)
+    return best
+
+
+def family_count(wl, fam):
+    """Planes of a family at the coarsest level."""
+    return len(top_list(wl, fam))
 
 
 def level_plan(wl, level):
-    """Per-level plane families: plane count, window size, lists, normals."""
+    """Per-level plane families: plane count, window size, lists, normals.
+    Level l has count * 2^(n-1-l) planes interpolated from the coarsest
+    list.  ``step`` is the inverse-distance step of lists uniform in inverse
+    distance (SGM^Pi-pg), None for other lists."""
     p = wl["params"]
     n = p["n_levels"]
     fams = wl["families"]
-    G = [family_count(wl, f) << (n - 1 - level) for f in fams]
+    tops = [top_list(wl, f) for f in fams]
+    G = [len(t) << (n - 1 - level) for t in tops]
     if level == n - 1 or p["window_labels"] <= 0:
         W = list(G)
     else:
         W = [min(int(p["window_labels"]), g) for g in G]
-    deltas = [plane_list(f["delta_min"], f["delta_max"], g) for f, g in zip(fams, G)]
+    deltas = [t.copy() if g == len(t) else level_list(t, g) for t, g in zip(tops, G)]
     fam_n = np.array([f["n"] for f in fams], np.float64)
-    inv_dmin = np.array([1.0 / f["delta_min"] for f in fams])
-    step = np.array([(1.0 / f["delta_min"] - 1.0 / f["delta_max"]) / (g - 1) if g > 1 else 1.0
-                     for f, g in zip(fams, G)])
-    return dict(G=G, W=W, deltas=deltas, fam_n=fam_n, inv_dmin=inv_dmin, step=step)
+    uniform = all(f.get("delta") is None and int(f["count"]) != 0 for f in fams)
+    step = None
+    if uniform:
+        step = np.array([(1.0 / d[0] - 1.0 / d[-1]) / (len(d) - 1) for d in deltas])
+    return dict(G=G, W=W, deltas=deltas, fam_n=fam_n, step=step)
 
 
 def subset_multiplier(side):
@@ -461,6 +525,8 @@ def run_frame(wl, keep=False, levels_only=None):
         fam_delta = np.concatenate(plan["deltas"])
         pg = None
         if p["sgm_variant"] == 2:
+            if plan["step"] is None:
+                raise ValueError("SGM^Pi-pg needs plane lists uniform in inverse distance")
             pg = dict(G=plan["G"], fam_delta=fam_delta, fam_n=plan["fam_n"], Kinv=Ki, step=plan["step"])
         Sbar, _ = sgm(S, plan["W"], p1, lut, img, p["n_paths"], offs=o, dI=dI if use_dI else None, pg=pg)
         label, fam, depth_raw = wta_refine(Sbar, plan["W"], plan["G"], plan["fam_n"], fam_delta, Ki, o)
@@ -479,9 +545,8 @@ def run_frame(wl, keep=False, levels_only=None):
             nbar = upsample_nn(nsm, fw, fh)
             Ki_f, _ = kinv_level(K, l - 1)
             plan_f = level_plan(wl, l - 1)
-            offs = window_offsets(dbar, Ki_f, plan_f["fam_n"], plan_f["inv_dmin"], plan_f["step"],
-                                  plan_f["G"], plan_f["W"])
-            dI = delta_i(dbar, nbar, Ki_f, plan_f["fam_n"], plan_f["step"]) if p["sgm_variant"] == 1 else None
+            offs = window_offsets(dbar, Ki_f, plan_f["fam_n"], plan_f["deltas"], plan_f["W"])
+            dI = delta_i(dbar, nbar, Ki_f, plan_f["fam_n"], plan_f["deltas"]) if p["sgm_variant"] == 1 else None
             if keep:
                 out["levels"][l]["seed"] = dict(dbar=dbar, nbar=nbar, offs=offs, dI=dI)
         if levels_only is not None and l == levels_only:

@@ -255,6 +255,45 @@ void or_plane_list(double delta_min, double delta_max, int G, double* delta) {
     for (int j = 0; j < G; ++j) delta[j] = 1.0 / (a - (double)j * step);
 }
 
+// Plane list of a finer level from the coarsest level's list top[0..Gt-1]
+// (increasing distances): Gl planes at the fractional indices
+// u_j = j (Gt - 1) / (Gl - 1) of the coarsest list, the inverse distance
+// interpolated linearly between the two neighbouring coarsest planes (a
+// plane at a whole index keeps its distance).  A list uniform in inverse
+// distance stays uniform; any other list keeps its spacing profile with
+// Gl / Gt times as many planes (reading of the per-level plane list with a
+// per-pixel sampling range, extended to the paper's lists of varying
+// distances).  Gl < Gt resamples a list down.  Returns -1 on bad sizes.
+int or_level_list(const double* top, int Gt, int Gl, double* out) {
+    if (Gt < 2 || Gl < 2) return -1;
+    for (int j = 0; j < Gl; ++j) {
+        long num = (long)j * (Gt - 1);
+        long i = num / (Gl - 1);
+        long rem = num - i * (Gl - 1);
+        if (rem == 0) {
+            out[j] = top[i];
+        } else {
+            double f = (double)rem / (double)(Gl - 1);
+            double a = 1.0 / top[i], b = 1.0 / top[i + 1];
+            out[j] = 1.0 / (a + f * (b - a));
+        }
+    }
+    return 0;
+}
+
+// Continuous index of the inverse distance iv in a plane list delta[0..G-1]
+// (increasing distances, so decreasing inverse distances): on the interval
+// between planes i and i+1 whose inverse distances enclose iv,
+// j = i + (1/delta_i - iv) / (1/delta_i - 1/delta_{i+1}); beyond the ends the
+// end interval is extended.  For a list uniform in inverse distance this is
+// (1/delta_0 - iv) / step.  The interval is found by a plain scan.
+double or_list_index(const double* delta, int G, double iv) {
+    int i = 0;
+    while (i + 2 < G && 1.0 / delta[i + 1] >= iv) ++i;
+    double a = 1.0 / delta[i], b = 1.0 / delta[i + 1];
+    return (double)i + (a - iv) / (a - b);
+}
+
 // Depth of pixel (x, y) on plane (n, delta): d = -delta / (n^T K^-1 p)
 // (depth extraction for SGM^Pi).  Returns 0 when the ray does not meet the
 // plane in front of the camera.
@@ -867,16 +906,19 @@ void or_upsample_nn(const float* src, int sw, int sh, int ch, int dw, int dh, fl
 }
 
 // Per-pixel sampling window: W consecutive planes of the level's list
-// (uniform in inverse distance, index 0 at delta_min) centred on the plane
-// through the seed depth along the pixel's ray; clamped to the list.  A pixel
-// without a seed (or whose ray misses the family's planes) gets the centre of
-// the list.  offs: [n_fam][h][w].
+// (index 0 at the nearest plane) centred on the plane through the seed depth
+// along the pixel's ray -- the rounded continuous index of that plane in the
+// list (or_list_index) -- clamped to the list.  A pixel without a seed (or
+// whose ray misses the family's planes) gets the centre of the list.
+//   fam_delta: the level's lists of all families, concatenated; offs:
+//   [n_fam][h][w].
 void or_window_offsets(const float* dbar, int w, int h, const double* Kinv, int n_fam, const double* fam_n,
-                       const double* inv_dmin, const double* step, const int* G, const int* W,
-                       int32_t* offs) {
+                       const double* fam_delta, const int* G, const int* W, int32_t* offs) {
     size_t N = (size_t)w * h;
+    int g0 = 0;
     for (int f = 0; f < n_fam; ++f) {
         const double* n = fam_n + 3 * f;
+        const double* list = fam_delta + g0;
         for (int y = 0; y < h; ++y)
             for (int x = 0; x < w; ++x) {
                 size_t p = (size_t)y * w + x;
@@ -889,28 +931,33 @@ void or_window_offsets(const float* dbar, int w, int h, const double* Kinv, int 
                     o = (G[f] - W[f]) / 2;
                 } else {
                     double delta = d * c;
-                    double j = (inv_dmin[f] - 1.0 / delta) / step[f];
+                    double j = or_list_index(list, G[f], 1.0 / delta);
                     j = std::min(std::max(j, -1.0e6), 1.0e6);
                     int jr = (int)std::floor(j + 0.5);
                     o = clampi(jr - W[f] / 2, 0, G[f] - W[f]);
                 }
                 offs[(size_t)f * N + p] = o;
             }
+        g0 += G[f];
     }
 }
 
 // Surface-normal index offset (Eq. sgm-smooth-sn): the tangent plane of the
 // seed point P = dbar K^-1 p with seed normal nbar meets the ray of the
 // predecessor q = p - r at depth d_T; di(p, r, f) is the plane-index
-// difference, in family f's list, between the point on q's ray and P,
-// rounded half away from zero and clamped to [-7, 7].  Zero where the seed is
-// missing or the construction degenerates.  dI: [8][h][w][n_fam].
+// difference, in family f's list, between the point on q's ray and P
+// (continuous indices of their inverse distances, or_list_index), rounded
+// half away from zero and clamped to [-7, 7].  Zero where the seed is
+// missing or the construction degenerates.  fam_delta: the level's lists,
+// concatenated; dI: [8][h][w][n_fam].
 void or_delta_i(const float* dbar, const float* nbar, int w, int h, const double* Kinv, int n_fam,
-                const double* fam_n, const double* step, int8_t* dI) {
+                const double* fam_n, const double* fam_delta, const int* G, int8_t* dI) {
     static const int DX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
     static const int DY[8] = {0, 0, 1, -1, 1, -1, -1, 1};
     size_t N = (size_t)w * h;
     std::memset(dI, 0, 8 * N * n_fam);
+    std::vector<int> g0(n_fam, 0);
+    for (int f = 1; f < n_fam; ++f) g0[f] = g0[f - 1] + G[f - 1];
     for (int y = 0; y < h; ++y)
         for (int x = 0; x < w; ++x) {
             size_t p = (size_t)y * w + x;
@@ -934,7 +981,8 @@ void or_delta_i(const float* dbar, const float* nbar, int w, int h, const double
                     if (!(cp > 0.0) || !(cq > 0.0)) continue;
                     double ip = 1.0 / (d * cp);
                     double iq = 1.0 / (dT * cq);
-                    double v = (ip - iq) / step[f];
+                    const double* list = fam_delta + g0[f];
+                    double v = or_list_index(list, G[f], iq) - or_list_index(list, G[f], ip);
                     v = std::min(std::max(v, -7.0), 7.0);
                     dI[((size_t)r * N + p) * n_fam + f] = (int8_t)std::round(v);
                 }

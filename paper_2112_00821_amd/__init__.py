@@ -54,7 +54,7 @@ class ServerResult(C.Structure):
 
 class PlaneFamily(C.Structure):
     _fields_ = [("n", C.c_double * 3), ("delta_min", C.c_double), ("delta_max", C.c_double),
-                ("count", C.c_int32)]
+                ("count", C.c_int32), ("delta", C.c_void_p), ("depth_min", C.c_double), ("depth_max", C.c_double)]
 
 
 _lib = None
@@ -116,7 +116,7 @@ def _declare(L):
         "fassmvs_stage_median": (st, [vp, vp, i32, i32, vp]),
         "fassmvs_stage_normals": (st, [vp, vp, vp, i32, i32, vp, i32, dbl, vp, vp, i32, vp, dbl, vp, vp, vp]),
         "fassmvs_stage_seed": (st, [vp, vp, vp, i32, i32, i32, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp,
-                                    vp, vp]),
+                                    vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -187,12 +187,27 @@ def cross_ratio_planes(K, w, h, R, t, n, delta_min, delta_max, max_planes=4096):
 
 
 def _families(families):
+    """ctypes array of plane families from dicts with 'n' and either
+    'delta' (an explicit coarsest list), 'delta_min'/'delta_max'/'count', or
+    'depth_min'/'depth_max' (bounding planes, delta range left 0).  The
+    returned array keeps the explicit lists alive."""
     fams = (PlaneFamily * len(families))()
+    keep = []
     for i, f in enumerate(families):
         fams[i].n[:] = [float(x) for x in f["n"]]
-        fams[i].delta_min = f["delta_min"]
-        fams[i].delta_max = f["delta_max"]
-        fams[i].count = int(f["count"])
+        fams[i].delta_min = float(f.get("delta_min", 0.0))
+        fams[i].delta_max = float(f.get("delta_max", 0.0))
+        fams[i].depth_min = float(f.get("depth_min", 0.0))
+        fams[i].depth_max = float(f.get("depth_max", 0.0))
+        if f.get("delta") is not None:
+            d = np.ascontiguousarray(f["delta"], np.float64)
+            keep.append(d)
+            fams[i].delta = d.ctypes.data
+            fams[i].count = len(d)
+        else:
+            fams[i].delta = None
+            fams[i].count = int(f["count"])
+    fams._lists = keep
     return fams
 
 
@@ -366,8 +381,9 @@ class Handle:
     # ---------------------------------------------------------------- frames
     def submit_frame(self, ref, views, side, K, families, mem_kind=MEM_HOST):
         """ref / views: dicts with 'img' (numpy uint8 HxW, or DeviceArray with
-        mem_kind=MEM_DEVICE), 'R' (3x3), 't' (3).  families: dicts with 'n',
-        'delta_min', 'delta_max', 'count'."""
+        mem_kind=MEM_DEVICE), 'R' (3x3), 't' (3).  families: dicts with 'n' and
+        'delta_min', 'delta_max', 'count', or an explicit list 'delta', or a
+        depth range 'depth_min', 'depth_max' (see _families)."""
         keep = []
 
         def mk(v):
@@ -390,12 +406,7 @@ class Handle:
         vs = (Image * len(views))(*[mk(v) for v in views])
         sd = (C.c_int8 * len(side))(*side)
         Kc = (C.c_double * 9)(*[float(x) for x in np.asarray(K, np.float64).ravel()])
-        fams = (PlaneFamily * len(families))()
-        for i, f in enumerate(families):
-            fams[i].n[:] = [float(x) for x in f["n"]]
-            fams[i].delta_min = f["delta_min"]
-            fams[i].delta_max = f["delta_max"]
-            fams[i].count = f["count"]
+        fams = _families(families)
         t = C.c_uint64()
         self._check(lib().fassmvs_submit_frame(self.h, C.byref(r), vs, sd, len(views), Kc, fams, len(families),
                                                mem_kind, C.byref(t)))
@@ -583,20 +594,21 @@ class Handle:
                                                 len(na), npp, rho_deg, nraw.vp, normal.vp, conf.vp))
         return nraw, normal, conf
 
-    def stage_seed(self, depth_c, normal_c, fw, fh, Kinv, fam_n, inv_dmin, step, G, W, want_dI=True):
+    def stage_seed(self, depth_c, normal_c, fw, fh, Kinv, fam_n, deltas, W, want_dI=True):
+        """deltas: the fine level's plane list of every family."""
         ch, cw = depth_c.shape
+        G = [len(d) for d in deltas]
         F = len(G)
         ka, kp = _arr(Kinv, np.float64)
         na, npp = _arr(fam_n, np.float64)
-        ia, ip = _arr(inv_dmin, np.float64)
-        sa, sp = _arr(step, np.float64)
+        da, dp = _arr(np.concatenate([np.asarray(d, np.float64) for d in deltas]), np.float64)
         Ga, Gp = _arr(G, np.int32)
         Wa, Wp = _arr(W, np.int32)
         dbar = self.empty((fh, fw), np.float32)
         nbar = self.empty((fh, fw, 3), np.float32)
         offs = self.empty((F, fh, fw), np.int32)
         dI = self.empty((8, fh, fw, F), np.int8) if want_dI else None
-        self._check(lib().fassmvs_stage_seed(self.h, depth_c.vp, normal_c.vp, cw, ch, fw, fh, kp, F, npp, ip, sp, Gp,
+        self._check(lib().fassmvs_stage_seed(self.h, depth_c.vp, normal_c.vp, cw, ch, fw, fh, kp, F, npp, dp, Gp,
                                              Wp, dbar.vp, nbar.vp, offs.vp, _vp(dI)))
         return dbar, nbar, offs, dI
 

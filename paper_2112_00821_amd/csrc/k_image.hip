@@ -291,11 +291,31 @@ hipError_t launch_normals(const NormalArgs &a, hipStream_t s) {
 }
 
 // --------------------------------------------------------------- seeds
+// Continuous index of the inverse distance iv in a plane list of G >= 2
+// increasing distances: bisection for the last interval start i in
+// [0, G-2] whose plane's inverse distance is >= iv (0 if none), then the
+// linear position inside that interval (end intervals extended beyond the
+// list).
+__device__ double list_index(const double *__restrict__ d, int G, double iv) {
+    int lo = 0, hi = G - 2;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (1.0 / d[mid] >= iv)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const double a = 1.0 / d[lo], b = 1.0 / d[lo + 1];
+    return (double)lo + (a - iv) / (a - b);
+}
+
 // Coarse-to-fine initialisation: nearest-neighbour upsampling of depth and
 // normal (fine (x,y) <- coarse (min(x/2, cw-1), min(y/2, ch-1))), the
 // per-family sampling windows centred on the plane through the seed depth
-// (Eq. sampling_range, dynamic cost volume), and the surface-normal index
-// offsets of Eq. sgm-smooth-sn toward each path predecessor q = p - r.
+// (Eq. sampling_range, dynamic cost volume) -- its rounded continuous index
+// in the level's list -- and the surface-normal index offsets of
+// Eq. sgm-smooth-sn toward each path predecessor q = p - r, as differences
+// of continuous indices.
 __global__ __launch_bounds__(256) void k_seed(const SeedArgs a) {
     int x = blockIdx.x * 16 + (threadIdx.x & 15);
     int y = blockIdx.y * 16 + (threadIdx.x >> 4);
@@ -320,7 +340,7 @@ __global__ __launch_bounds__(256) void k_seed(const SeedArgs a) {
             o = (a.G[f] - a.W[f]) / 2;
         } else {
             double delta = d * c;
-            double j = (a.inv_dmin[f] - 1.0 / delta) / a.step[f];
+            double j = list_index(a.delta + a.goff[f], a.G[f], 1.0 / delta);
             j = fmin(fmax(j, -1.0e6), 1.0e6);
             int jr = (int)floor(j + 0.5);
             o = clampi(jr - a.W[f] / 2, 0, a.G[f] - a.W[f]);
@@ -347,7 +367,8 @@ __global__ __launch_bounds__(256) void k_seed(const SeedArgs a) {
             if (!(cp > 0.0) || !(cq > 0.0)) continue;
             double ip = 1.0 / (d * cp);
             double iq = 1.0 / (dT * cq);
-            double v = (ip - iq) / a.step[f];
+            const double *list = a.delta + a.goff[f];
+            double v = list_index(list, a.G[f], iq) - list_index(list, a.G[f], ip);
             v = fmin(fmax(v, -7.0), 7.0);
             a.dI[((size_t)r * N + p) * a.n_fam + f] = (int8_t)round(v);
         }

@@ -117,7 +117,8 @@ struct SeedArgs {
     int cw, ch, fw, fh, n_fam;
     double Kinv[9];
     double fam_n[kMaxFam][3];
-    double inv_dmin[kMaxFam], step[kMaxFam];
+    const double *delta;      // the fine level's plane lists, concatenated (device)
+    int goff[kMaxFam];        // first plane of each family in delta
     int G[kMaxFam], W[kMaxFam];
     const float *depth_c, *normal_c;
     float *dbar, *nbar;
@@ -148,5 +149,6 @@ struct GeoArgs {
     int eta_h;
 };
 hipError_t launch_geo(const GeoArgs &a, int32_t *hits, uint8_t *keep, hipStream_t s);
+
 
 }  // namespace fmvs

@@ -18,6 +18,7 @@
 
 #include "../../include/fassmvs.h"
 #include "kernels.hpp"
+#include "handle_internal.hpp"
 
 using namespace fmvs;
 
@@ -56,7 +57,7 @@ struct LevelPlan {
     double K[9], Kinv[9];
     int F = 0, D = 0, sumG = 0;
     int G[kMaxFam], W[kMaxFam], foff[kMaxFam], goff[kMaxFam];
-    double inv_dmin[kMaxFam], step[kMaxFam];
+    double step[kMaxFam];   // inverse-distance step (lists uniform in 1/delta; path-gradient SGM)
     bool windows = false, sn = false;
     size_t h_off = 0;   // offset (doubles) of this level's homographies in the parameter blob
     size_t d_off = 0;   // offset (doubles) of this level's plane lists
@@ -99,6 +100,7 @@ struct fassmvs_handle {
 
     // device buffers
     size_t held = 0;
+    bool exact_growth = false;
     DevBuf pyr[kMaxViews + 1];       // every level of each image, level 0 first
     DevBuf ct, S, wta, c3, params, work_ctr;
     DevBuf sgmbuf[8];
@@ -143,7 +145,9 @@ fassmvs_status dev_fail(fassmvs_handle *h, hipError_t e, const char *what) {
 fassmvs_status ensure(fassmvs_handle *h, DevBuf &b, size_t bytes) {
     if (bytes == 0) bytes = 256;
     if (b.bytes >= bytes) return FASSMVS_OK;
-    size_t want = bytes + bytes / 8;   // some headroom for the next, larger frame
+    // some headroom for the next, larger frame (not for server slots, whose
+    // admission counts the exact growth)
+    size_t want = h->exact_growth ? bytes : bytes + bytes / 8;
     if (h->cfg.hbm_budget_bytes && h->held - b.bytes + want > h->cfg.hbm_budget_bytes) {
         want = bytes;
         if (h->held - b.bytes + want > h->cfg.hbm_budget_bytes)
@@ -236,60 +240,100 @@ bool finite_all(const double *v, int n) {
 }
 
 // ------------------------------------------------------------- geometry
-// Inverse of the upper-triangular intrinsic matrix at level l (focal
-// lengths, skew and principal point scaled by 2^-l), in closed form.
+// Intrinsics of pyramid level l (focal lengths, skew and principal point
+// scaled by 2^-l, exact) and their inverse by back substitution on the
+// upper-triangular matrix.
 bool kinv_level(const double *K, int level, double *Kl, double *Ki) {
     if (K[3] != 0.0 || K[6] != 0.0 || K[7] != 0.0 || K[8] != 1.0) return false;
-    double sc = std::ldexp(1.0, -level);
-    double fx = K[0] * sc, s = K[1] * sc, cx = K[2] * sc, fy = K[4] * sc, cy = K[5] * sc;
-    if (!(fx > 0.0) || !(fy > 0.0)) return false;
-    Ki[0] = 1.0 / fx;
-    Ki[1] = -s / (fx * fy);
-    Ki[2] = (s * cy - cx * fy) / (fx * fy);
-    Ki[3] = 0.0;
-    Ki[4] = 1.0 / fy;
-    Ki[5] = -cy / fy;
+    const double sc = std::ldexp(1.0, -level);
+    for (int i = 0; i < 9; ++i) Kl[i] = i == 8 ? 1.0 : K[i] * sc;
+    if (!(Kl[0] > 0.0) || !(Kl[4] > 0.0)) return false;
+    // rows from the bottom: Ki = K^-1 with K = [fx s cx; 0 fy cy; 0 0 1]
+    const double ify = 1.0 / Kl[4], ifx = 1.0 / Kl[0];
     Ki[6] = 0.0;
     Ki[7] = 0.0;
     Ki[8] = 1.0;
-    const double kl[9] = {fx, s, cx, 0.0, fy, cy, 0.0, 0.0, 1.0};
-    std::memcpy(Kl, kl, sizeof(kl));
+    Ki[3] = 0.0;
+    Ki[4] = ify;
+    Ki[5] = -Kl[5] * ify;
+    Ki[0] = ifx;
+    Ki[1] = -Kl[1] * Ki[4] * ifx;
+    Ki[2] = -(Kl[1] * Ki[5] + Kl[2]) * ifx;
     return true;
 }
 
-// [R|t] of view k relative to the reference: R = R_k R_ref^T, t = t_k - R t_ref.
+// Pose of view k relative to the reference camera: R = R_k R_ref^T and, with
+// the camera centres C = -R^T t of both cameras, t = R_k (C_ref - C_k), so
+// that x_k = R x_ref + t.
 void relative_pose(const double *Rr, const double *tr, const double *Rk, const double *tk, double *R, double *t) {
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            double s = 0.0;
-            for (int k = 0; k < 3; ++k) s += Rk[i * 3 + k] * Rr[j * 3 + k];
-            R[i * 3 + j] = s;
-        }
+    double Cr[3], Ck[3], d[3];
     for (int i = 0; i < 3; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < 3; ++j) s += R[i * 3 + j] * tr[j];
-        t[i] = tk[i] - s;
+        Cr[i] = -(Rr[i] * tr[0] + Rr[3 + i] * tr[1] + Rr[6 + i] * tr[2]);
+        Ck[i] = -(Rk[i] * tk[0] + Rk[3 + i] * tk[1] + Rk[6 + i] * tk[2]);
+    }
+    for (int i = 0; i < 3; ++i) d[i] = Cr[i] - Ck[i];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) R[r * 3 + c] = Rk[r * 3] * Rr[c * 3] + Rk[r * 3 + 1] * Rr[c * 3 + 1] + Rk[r * 3 + 2] * Rr[c * 3 + 2];
+        t[r] = Rk[r * 3] * d[0] + Rk[r * 3 + 1] * d[1] + Rk[r * 3 + 2] * d[2];
     }
 }
 
-// Plane-induced homography K (R - t n^T / delta) K^-1 (Eq. homography).
-void homography(const double *K, const double *Ki, const double *R, const double *t, const double *n, double delta,
-                double *H) {
-    double M[9], A[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) M[i * 3 + j] = R[i * 3 + j] - t[i] * n[j] / delta;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            double s = 0.0;
-            for (int k = 0; k < 3; ++k) s += K[i * 3 + k] * M[k * 3 + j];
-            A[i * 3 + j] = s;
+// Plane-induced homographies of one view at one level (Eq. homography),
+// in the form the sweep's plane loop wants: for planes n^T X + delta = 0 of
+// one family, H(delta) = A + (1/delta) B with A = K R K^-1 (the homography
+// at infinity) and the rank-1 B = -(K t)(K^-T n)^T, since
+// K (R - t n^T / delta) K^-1 = K R K^-1 - (K t)(n^T K^-1) / delta.
+struct ViewGeom {
+    double A[9];    // K R K^-1
+    double Kt[3];   // K t
+};
+
+void view_geom(const double *K, const double *Ki, const double *R, const double *t, ViewGeom &g) {
+    double KR[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) KR[r * 3 + c] = K[r * 3] * R[c] + K[r * 3 + 1] * R[3 + c] + K[r * 3 + 2] * R[6 + c];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c)
+            g.A[r * 3 + c] = KR[r * 3] * Ki[c] + KR[r * 3 + 1] * Ki[3 + c] + KR[r * 3 + 2] * Ki[6 + c];
+        g.Kt[r] = K[r * 3] * t[0] + K[r * 3 + 1] * t[1] + K[r * 3 + 2] * t[2];
+    }
+}
+
+// B = -(K t)(n^T K^-1): the part of the homography that scales with 1/delta.
+void family_term(const ViewGeom &g, const double *Ki, const double *n, double *B) {
+    double nK[3];
+    for (int c = 0; c < 3; ++c) nK[c] = n[0] * Ki[c] + n[1] * Ki[3 + c] + n[2] * Ki[6 + c];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) B[r * 3 + c] = -g.Kt[r] * nK[c];
+}
+
+// ------------------------------------------------------------- plane lists
+// The coarsest list of a family with count planes uniform in inverse
+// distance over [lo, hi] (index 0 at the nearest plane).
+void uniform_list(double lo, double hi, int count, double *out) {
+    const double near_inv = 1.0 / lo;
+    const double step = (near_inv - 1.0 / hi) / (double)(count - 1);
+    for (int j = 0; j < count; ++j) out[j] = 1.0 / (near_inv - (double)j * step);
+}
+
+// A list of G planes from a list top[0..Gt-1] of increasing distances:
+// plane j sits at the fractional index j (Gt - 1) / (G - 1) of top; between
+// two planes of top the inverse distance runs linearly, and a plane at a
+// whole index keeps top's distance.  Finer levels refine the coarsest list
+// this way; a list longer than the 256-plane cap is resampled the same way.
+void resample_list(const double *top, int Gt, int G, double *out) {
+    const long den = G - 1;
+    for (int j = 0; j < G; ++j) {
+        const long pos = (long)j * (Gt - 1);
+        const long k = pos / den, frac = pos % den;
+        if (frac == 0) {
+            out[j] = top[k];
+            continue;
         }
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            double s = 0.0;
-            for (int k = 0; k < 3; ++k) s += A[i * 3 + k] * Ki[k * 3 + j];
-            H[i * 3 + j] = s;
-        }
+        const double u = (double)frac / (double)den;
+        const double i0 = 1.0 / top[k], i1 = 1.0 / top[k + 1];
+        out[j] = 1.0 / (i0 + u * (i1 - i0));
+    }
 }
 
 // Parameters of the DoG texture filter: 7x7 Gaussian with sigma
@@ -459,46 +503,77 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
     // relative poses and camera centres in reference coordinates
     double Rrel[kMaxViews][9], trel[kMaxViews][3];
     for (int k = 0; k < n_views; ++k) relative_pose(ref->R, ref->t, views[k].R, views[k].t, Rrel[k], trel[k]);
+    // coarsest-level plane list of every family, increasing distances
+    double Kt[9], Kti[9];
+    if (!kinv_level(K, c.n_levels - 1, Kt, Kti)) return fail(h, FASSMVS_EINVAL, "K must have positive focal lengths");
+    const int wt = w >> (c.n_levels - 1), ht = hh >> (c.n_levels - 1);
+    std::vector<double> top[kMaxFam];
+    bool all_uniform = true;
     for (int f = 0; f < F; ++f) {
         const fassmvs_plane_family &pf = fam[f];
         double nn = pf.n[0] * pf.n[0] + pf.n[1] * pf.n[1] + pf.n[2] * pf.n[2];
         if (!finite_all(pf.n, 3) || std::fabs(nn - 1.0) > 1e-6 || !(pf.n[2] < 0.0))
             return fail(h, FASSMVS_EINVAL, "plane normals must be unit vectors facing the camera");
-        if (!(pf.delta_min > 0.0) || !(pf.delta_max > pf.delta_min) || !std::isfinite(pf.delta_max))
-            return fail(h, FASSMVS_EINVAL, "plane distances need 0 < delta_min < delta_max");
-        if (pf.count != 0 && (pf.count < 2 || pf.count > FASSMVS_MAX_TOP_PLANES))
-            return fail(h, FASSMVS_EINVAL, "plane count at the coarsest level must be 0 or 2..256");
         for (int i = 0; i < 3; ++i) P.fam_n[f][i] = pf.n[i];
+        if (pf.delta) {
+            if (pf.count < 2 || pf.count > FASSMVS_MAX_TOP_PLANES)
+                return fail(h, FASSMVS_EINVAL, "an explicit plane list needs 2..256 distances");
+            top[f].assign(pf.delta, pf.delta + pf.count);
+            if (top[f].front() > top[f].back()) std::reverse(top[f].begin(), top[f].end());
+            for (int j = 0; j < pf.count; ++j)
+                if (!std::isfinite(top[f][j]) || !(top[f][j] > 0.0) || (j > 0 && !(top[f][j] > top[f][j - 1])))
+                    return fail(h, FASSMVS_EINVAL, "plane distances must be positive and strictly monotone");
+            all_uniform = false;
+        } else {
+            double lo = pf.delta_min, hi = pf.delta_max;
+            if (lo == 0.0 && hi == 0.0) {
+                // bounding planes of the depth range over the reference frustum
+                double bp[2];
+                if (fassmvs_bounding_planes(K, w, hh, pf.n, pf.depth_min, pf.depth_max, bp) != FASSMVS_OK)
+                    return fail(h, FASSMVS_EINVAL, "a family without distances needs 0 < depth_min < depth_max");
+                lo = bp[0];
+                hi = bp[1];
+            }
+            if (!(lo > 0.0) || !(hi > lo) || !std::isfinite(hi))
+                return fail(h, FASSMVS_EINVAL, "plane distances need 0 < delta_min < delta_max");
+            if (pf.count != 0) {
+                if (pf.count < 2 || pf.count > FASSMVS_MAX_TOP_PLANES)
+                    return fail(h, FASSMVS_EINVAL, "plane count at the coarsest level must be 0 or 2..256");
+                top[f].resize(pf.count);
+                uniform_list(lo, hi, pf.count, top[f].data());
+            } else {
+                // the cross-ratio list of the view whose list is longest
+                all_uniform = false;
+                std::vector<double> best;
+                for (int k = 0; k < n_views; ++k) {
+                    double probe[1];
+                    const int len = cross_ratio_list(Kt, wt, ht, Rrel[k], trel[k], pf.n, lo, hi, 0, probe);
+                    if (len <= (int)best.size()) continue;
+                    std::vector<double> lst(len);
+                    cross_ratio_list(Kt, wt, ht, Rrel[k], trel[k], pf.n, lo, hi, len, lst.data());
+                    best.swap(lst);
+                }
+                if (best.size() < 2) return fail(h, FASSMVS_EINVAL, "no cross-ratio plane list for a family with count 0");
+                std::reverse(best.begin(), best.end());
+                if (best.size() > (size_t)FASSMVS_MAX_TOP_PLANES) {
+                    top[f].resize(FASSMVS_MAX_TOP_PLANES);
+                    resample_list(best.data(), (int)best.size(), FASSMVS_MAX_TOP_PLANES, top[f].data());
+                } else {
+                    top[f].swap(best);
+                }
+            }
+        }
         // every camera centre in front of the nearest plane
         for (int k = 0; k < n_views; ++k) {
             double C[3];
             for (int i = 0; i < 3; ++i)
                 C[i] = -(Rrel[k][0 * 3 + i] * trel[k][0] + Rrel[k][1 * 3 + i] * trel[k][1] + Rrel[k][2 * 3 + i] * trel[k][2]);
-            if (!(pf.n[0] * C[0] + pf.n[1] * C[1] + pf.n[2] * C[2] + pf.delta_min > 0.0))
+            if (!(pf.n[0] * C[0] + pf.n[1] * C[1] + pf.n[2] * C[2] + top[f].front() > 0.0))
                 return fail(h, FASSMVS_EINVAL, "a camera centre lies behind the nearest sweep plane");
         }
     }
-    // coarsest-level plane counts; count 0 takes the cross-ratio list's
-    // length for the view with the longest epipolar segment
-    int fam_count[kMaxFam];
-    {
-        double Kt[9], Kti[9];
-        if (!kinv_level(K, c.n_levels - 1, Kt, Kti)) return fail(h, FASSMVS_EINVAL, "K must have positive focal lengths");
-        const int wt = w >> (c.n_levels - 1), ht = hh >> (c.n_levels - 1);
-        for (int f = 0; f < F; ++f) {
-            fam_count[f] = fam[f].count;
-            if (fam_count[f] != 0) continue;
-            int best = 0;
-            for (int k = 0; k < n_views; ++k) {
-                double tmp[1];
-                const int len = cross_ratio_list(Kt, wt, ht, Rrel[k], trel[k], fam[f].n, fam[f].delta_min,
-                                                 fam[f].delta_max, 1, tmp);
-                best = std::max(best, len);
-            }
-            if (best < 2) return fail(h, FASSMVS_EINVAL, "no cross-ratio plane list for a family with count 0");
-            fam_count[f] = std::min(best, (int)FASSMVS_MAX_TOP_PLANES);
-        }
-    }
+    if (c.sgm_variant == 2 && !all_uniform)
+        return fail(h, FASSMVS_EUNSUPPORTED, "SGM^Pi-pg needs plane lists uniform in inverse distance");
     // penalties: P1 and P2 scaled like the cost
     P.p1 = mpen * c.p1;
     int p2max = 0;
@@ -519,12 +594,12 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
         L.h = l == 0 ? hh : P.lv[l - 1].h / 2;
         if (!kinv_level(K, l, L.K, L.Kinv)) return fail(h, FASSMVS_EINVAL, "K must have positive focal lengths");
         L.F = F;
-        const bool top = l == c.n_levels - 1;
-        L.windows = !top && c.window_labels > 0;
-        L.sn = !top && c.sgm_variant == 1;
+        const bool coarsest = l == c.n_levels - 1;
+        L.windows = !coarsest && c.window_labels > 0;
+        L.sn = !coarsest && c.sgm_variant == 1;
         int D = 0, sumG = 0;
         for (int f = 0; f < F; ++f) {
-            long G = (long)fam_count[f] << (c.n_levels - 1 - l);
+            long G = (long)top[f].size() << (c.n_levels - 1 - l);
             if (G > 65535) return fail(h, FASSMVS_EUNSUPPORTED, "plane list too long");
             L.G[f] = (int)G;
             L.W[f] = L.windows ? std::min(c.window_labels, L.G[f]) : L.G[f];
@@ -532,8 +607,6 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
             L.goff[f] = sumG;
             D += L.W[f];
             sumG += L.G[f];
-            L.inv_dmin[f] = 1.0 / fam[f].delta_min;
-            L.step[f] = (L.inv_dmin[f] - 1.0 / fam[f].delta_max) / (double)(L.G[f] - 1);
         }
         if (D > FASSMVS_MAX_LABELS) return fail(h, FASSMVS_EUNSUPPORTED, "more than 512 labels per pixel at a level");
         L.D = D;
@@ -554,16 +627,31 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
         LevelPlan &L = P.lv[l];
         double *dl = P.blob.data() + L.d_off;
         for (int f = 0; f < F; ++f) {
-            double a = L.inv_dmin[f];
-            for (int j = 0; j < L.G[f]; ++j) dl[L.goff[f] + j] = 1.0 / (a - (double)j * L.step[f]);
+            double *lst = dl + L.goff[f];
+            const int Gt = (int)top[f].size();
+            if (L.G[f] == Gt)
+                std::copy(top[f].begin(), top[f].end(), lst);
+            else
+                resample_list(top[f].data(), Gt, L.G[f], lst);
+            for (int j = 1; j < L.G[f]; ++j)
+                if (!(lst[j] > lst[j - 1])) return fail(h, FASSMVS_EINVAL, "plane list too dense at a finer level");
+            // inverse-distance step of a uniform list (path-gradient SGM)
+            L.step[f] = (1.0 / lst[0] - 1.0 / lst[L.G[f] - 1]) / (double)(L.G[f] - 1);
         }
-        for (int k = 0; k < n_views; ++k)
-            for (int f = 0; f < F; ++f)
+        for (int k = 0; k < n_views; ++k) {
+            ViewGeom g;
+            view_geom(L.K, L.Kinv, Rrel[k], trel[k], g);
+            for (int f = 0; f < F; ++f) {
+                double B[9];
+                family_term(g, L.Kinv, P.fam_n[f], B);
                 for (int j = 0; j < L.G[f]; ++j) {
                     double *H = P.blob.data() + L.h_off + ((size_t)k * L.sumG + L.goff[f] + j) * 9;
-                    homography(L.K, L.Kinv, Rrel[k], trel[k], P.fam_n[f], dl[L.goff[f] + j], H);
+                    const double iv = 1.0 / dl[L.goff[f] + j];
+                    for (int e = 0; e < 9; ++e) H[e] = g.A[e] + iv * B[e];
                     if (!finite_all(H, 9)) return fail(h, FASSMVS_EINVAL, "degenerate homography");
                 }
+            }
+        }
     }
     return FASSMVS_OK;
 }
@@ -578,40 +666,51 @@ size_t pyr_total(int w, int hh, int levels) {
     return s;
 }
 
-fassmvs_status alloc_frame(fassmvs_handle *h, const FramePlan &P) {
+// Every device buffer a frame needs and its size in bytes.
+void frame_buffers(fassmvs_handle *h, const FramePlan &P, std::vector<std::pair<DevBuf *, size_t>> &out) {
     const fassmvs_config &c = h->cfg;
     const size_t N0 = (size_t)P.w * P.h;
-    size_t Dmax = 0, NDmax = 0;
-    for (int l = 0; l < P.n_levels; ++l) {
-        Dmax = std::max(Dmax, (size_t)P.lv[l].D);
-        NDmax = std::max(NDmax, (size_t)P.lv[l].w * P.lv[l].h * P.lv[l].D);
+    size_t NDmax = 0;
+    for (int l = 0; l < P.n_levels; ++l) NDmax = std::max(NDmax, (size_t)P.lv[l].w * P.lv[l].h * P.lv[l].D);
+    const size_t pyr = pyr_total(P.w, P.h, P.n_levels);
+    out.clear();
+    for (int i = 0; i <= P.n_views; ++i) out.emplace_back(&h->pyr[i], pyr);
+    out.emplace_back(&h->ct, N0 * 8);
+    out.emplace_back(&h->S, NDmax);
+    for (int i = 0; i < c.n_paths; ++i) out.emplace_back(&h->sgmbuf[i], NDmax * 2);
+    if (c.sgm_debug) out.emplace_back(&h->sbar, NDmax * 2);
+    out.emplace_back(&h->wta, N0 * 2);
+    if (c.dog_filter) {
+        out.emplace_back(&h->post_tmp, N0 * 8);
+        out.emplace_back(&h->post_m0, N0);
+        out.emplace_back(&h->post_m1, N0);
     }
-    fassmvs_status st;
-    size_t pyr = pyr_total(P.w, P.h, P.n_levels);
-    for (int i = 0; i <= P.n_views; ++i)
-        if ((st = ensure(h, h->pyr[i], pyr)) != FASSMVS_OK) return st;
-    if ((st = ensure(h, h->ct, N0 * 8)) != FASSMVS_OK) return st;
-    if ((st = ensure(h, h->S, NDmax)) != FASSMVS_OK) return st;
-    for (int i = 0; i < c.n_paths; ++i)
-        if ((st = ensure(h, h->sgmbuf[i], NDmax * 2)) != FASSMVS_OK) return st;
-    if (c.sgm_debug && (st = ensure(h, h->sbar, NDmax * 2)) != FASSMVS_OK) return st;
-    if ((st = ensure(h, h->wta, N0 * 2)) != FASSMVS_OK) return st;
-    if (c.dog_filter && ((st = ensure(h, h->post_tmp, N0 * 8)) || (st = ensure(h, h->post_m0, N0)) ||
-                         (st = ensure(h, h->post_m1, N0))))
-        return st;
-    if ((st = ensure(h, h->c3, N0 * 6)) != FASSMVS_OK) return st;
-    if ((st = ensure(h, h->params, P.blob.size() * 8)) != FASSMVS_OK) return st;
-    if ((st = ensure(h, h->work_ctr, 8)) != FASSMVS_OK) return st;
+    out.emplace_back(&h->c3, N0 * 6);
+    out.emplace_back(&h->params, P.blob.size() * 8);
+    out.emplace_back(&h->work_ctr, 8);
     for (int l = 0; l < P.n_levels; ++l) {
-        size_t N = (size_t)P.lv[l].w * P.lv[l].h;
+        const size_t N = (size_t)P.lv[l].w * P.lv[l].h;
         auto &B = h->lb[l];
-        if ((st = ensure(h, B.depth_raw, N * 4)) || (st = ensure(h, B.depth, N * 4)) ||
-            (st = ensure(h, B.nraw, N * 12)) || (st = ensure(h, B.normal, N * 12)) || (st = ensure(h, B.conf, N * 4)) ||
-            (st = ensure(h, B.label, N * 4)) || (st = ensure(h, B.fam, N * 4)) ||
-            (st = ensure(h, B.offs, N * 4 * P.F)) || (st = ensure(h, B.dI, N * 8 * P.F)) ||
-            (st = ensure(h, B.dbar, N * 4)) || (st = ensure(h, B.nbar, N * 12)))
-            return st;
+        out.emplace_back(&B.depth_raw, N * 4);
+        out.emplace_back(&B.depth, N * 4);
+        out.emplace_back(&B.nraw, N * 12);
+        out.emplace_back(&B.normal, N * 12);
+        out.emplace_back(&B.conf, N * 4);
+        out.emplace_back(&B.label, N * 4);
+        out.emplace_back(&B.fam, N * 4);
+        out.emplace_back(&B.offs, N * 4 * P.F);
+        out.emplace_back(&B.dI, N * 8 * P.F);
+        out.emplace_back(&B.dbar, N * 4);
+        out.emplace_back(&B.nbar, N * 12);
     }
+}
+
+fassmvs_status alloc_frame(fassmvs_handle *h, const FramePlan &P) {
+    std::vector<std::pair<DevBuf *, size_t>> bufs;
+    frame_buffers(h, P, bufs);
+    fassmvs_status st;
+    for (auto &b : bufs)
+        if ((st = ensure(h, *b.first, b.second)) != FASSMVS_OK) return st;
     size_t pin = pyr_total(P.w, P.h, 1) * (P.n_views + 1) + P.blob.size() * 8 + 64;
     if (h->pin_bytes < pin) {
         if (h->pin) hipHostFree(h->pin);
@@ -847,11 +946,11 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
             std::memcpy(a.Kinv, Lf.Kinv, sizeof(a.Kinv));
             for (int f = 0; f < Lf.F; ++f) {
                 for (int i = 0; i < 3; ++i) a.fam_n[f][i] = P.fam_n[f][i];
-                a.inv_dmin[f] = Lf.inv_dmin[f];
-                a.step[f] = Lf.step[f];
+                a.goff[f] = Lf.goff[f];
                 a.G[f] = Lf.G[f];
                 a.W[f] = Lf.W[f];
             }
+            a.delta = dblob + Lf.d_off;
             a.depth_c = (const float *)B.depth.p;
             a.normal_c = (const float *)B.normal.p;
             a.dbar = (float *)Bf.dbar.p;
@@ -883,7 +982,7 @@ fassmvs_status fassmvs_frame_footprint(const fassmvs_config *cfg, int32_t w, int
     if (!cfg || !families || !bytes || w < 1 || hgt < 1 || n_views < 1 || n_views > kMaxViews || n_families < 1 ||
         n_families > kMaxFam || cfg->n_levels < 1 || cfg->n_levels > FASSMVS_MAX_LEVELS)
         return FASSMVS_EINVAL;
-    size_t NDmax = 0, maps = 0;
+    size_t NDmax = 0, maps = 0, params = 0;
     int lw = w, lh = hgt;
     for (int l = 0; l < cfg->n_levels; ++l) {
         if (l > 0) {
@@ -892,10 +991,12 @@ fassmvs_status fassmvs_frame_footprint(const fassmvs_config *cfg, int32_t w, int
         }
         size_t D = 0;
         for (int f = 0; f < n_families; ++f) {
+            // an explicit list has count entries; count 0 is counted at the cap
             const size_t count = families[f].count > 0 ? (size_t)families[f].count : (size_t)FASSMVS_MAX_TOP_PLANES;
             const size_t G = count << (cfg->n_levels - 1 - l);
             const bool windows = l < cfg->n_levels - 1 && cfg->window_labels > 0;
             D += windows ? std::min((size_t)cfg->window_labels, G) : G;
+            params += G * ((size_t)n_views * 9 + 1) * 8;   // homographies and the plane list
         }
         const size_t N = (size_t)lw * lh;
         NDmax = std::max(NDmax, N * D);
@@ -905,7 +1006,7 @@ fassmvs_status fassmvs_frame_footprint(const fassmvs_config *cfg, int32_t w, int
     }
     const size_t N0 = (size_t)w * hgt;
     size_t total = NDmax * (1 + 2 * (size_t)cfg->n_paths) + maps + pyr_total(w, hgt, cfg->n_levels) * (n_views + 1) +
-                   N0 * (8 + 2 + 6);
+                   N0 * (8 + 2 + 6) + params + 256;
     if (cfg->sgm_debug) total += NDmax * 2;
     if (cfg->dog_filter) total += N0 * 10;
     *bytes = total;
@@ -1070,6 +1171,74 @@ fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref,
     *ticket = h->ticket;
     return FASSMVS_OK;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- for the served form
+namespace fmvs {
+
+void handle_set_exact_growth(fassmvs_handle *h) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->exact_growth = true;
+}
+
+uint64_t handle_held(fassmvs_handle *h) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    return h->held;
+}
+
+fassmvs_status handle_growth(fassmvs_handle *h, const fassmvs_image *ref, const fassmvs_image *views,
+                             const int8_t *side, int32_t n_views, const double K[9],
+                             const fassmvs_plane_family *families, int32_t n_families, uint64_t *grow) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    FramePlan P;
+    fassmvs_status st = make_plan(h, ref, views, side, n_views, K, families, n_families, P);
+    if (st != FASSMVS_OK) return st;
+    std::vector<std::pair<DevBuf *, size_t>> bufs;
+    frame_buffers(h, P, bufs);
+    uint64_t g = 0;
+    for (auto &b : bufs) {
+        const size_t need = b.second == 0 ? 256 : b.second;
+        if (b.first->bytes >= need) continue;
+        g += (h->exact_growth ? need : need + need / 8) - b.first->bytes;
+    }
+    *grow = g;
+    return FASSMVS_OK;
+}
+
+void handle_trim(fassmvs_handle *h) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (h->busy) return;
+    hipSetDevice(h->cfg.device);
+    hipStreamSynchronize(h->stream);
+    auto drop = [&](DevBuf &b) {
+        if (b.p) hipFree(b.p);
+        h->held -= b.bytes;
+        b = DevBuf();
+    };
+    for (auto &b : h->pyr) drop(b);
+    drop(h->ct);
+    drop(h->S);
+    drop(h->wta);
+    drop(h->c3);
+    drop(h->params);
+    drop(h->work_ctr);
+    for (auto &b : h->sgmbuf) drop(b);
+    drop(h->sbar);
+    drop(h->post_tmp);
+    drop(h->post_m0);
+    drop(h->post_m1);
+    drop(h->post_hits);
+    for (auto &L : h->lb) {
+        for (DevBuf *b : {&L.depth_raw, &L.depth, &L.nraw, &L.normal, &L.conf, &L.label, &L.fam, &L.offs, &L.dI,
+                          &L.dbar, &L.nbar})
+            drop(*b);
+    }
+}
+
+}  // namespace fmvs
+
+extern "C" {
 
 fassmvs_status fassmvs_poll(fassmvs_handle *h, uint64_t ticket, float *depth, float *normal, float *confidence,
                             int32_t mem_kind, int32_t wait_ms) {
@@ -1658,10 +1827,10 @@ fassmvs_status fassmvs_stage_normals(fassmvs_handle *h, const float *depth, cons
 
 fassmvs_status fassmvs_stage_seed(fassmvs_handle *h, const float *depth_c, const float *normal_c, int32_t cw,
                                   int32_t ch, int32_t fw, int32_t fh, const double *Kinv, int32_t n_fam,
-                                  const double *fam_n, const double *inv_dmin, const double *step, const int32_t *G,
-                                  const int32_t *W, float *dbar, float *nbar, int32_t *offs, int8_t *dI) {
+                                  const double *fam_n, const double *fam_delta, const int32_t *G, const int32_t *W,
+                                  float *dbar, float *nbar, int32_t *offs, int8_t *dI) {
     STAGE_BEGIN;
-    if (!depth_c || !normal_c || !Kinv || !fam_n || !inv_dmin || !step || !G || !W || !dbar || !nbar || !offs ||
+    if (!depth_c || !normal_c || !Kinv || !fam_n || !fam_delta || !G || !W || !dbar || !nbar || !offs ||
         n_fam < 1 || n_fam > kMaxFam || cw < 1 || ch < 1 || fw < 1 || fh < 1)
         return fail(h, FASSMVS_EINVAL, "bad seed arguments");
     SeedArgs a;
@@ -1672,14 +1841,22 @@ fassmvs_status fassmvs_stage_seed(fassmvs_handle *h, const float *depth_c, const
     a.fh = fh;
     a.n_fam = n_fam;
     std::memcpy(a.Kinv, Kinv, 72);
+    int sumG = 0;
     for (int f = 0; f < n_fam; ++f) {
-        if (W[f] < 1 || W[f] > G[f]) return fail(h, FASSMVS_EINVAL, "bad family sizes");
+        if (G[f] < 2 || W[f] < 1 || W[f] > G[f]) return fail(h, FASSMVS_EINVAL, "bad family sizes");
         for (int i = 0; i < 3; ++i) a.fam_n[f][i] = fam_n[f * 3 + i];
-        a.inv_dmin[f] = inv_dmin[f];
-        a.step[f] = step[f];
+        a.goff[f] = sumG;
         a.G[f] = G[f];
         a.W[f] = W[f];
+        sumG += G[f];
     }
+    for (int j = 0; j < sumG; ++j)
+        if (!(fam_delta[j] > 0.0) || !std::isfinite(fam_delta[j])) return fail(h, FASSMVS_EINVAL, "bad plane list");
+    fassmvs_status st = ensure(h, h->params, (size_t)sumG * 8);
+    if (st != FASSMVS_OK) return st;
+    HIPCHK(h, hipMemcpyAsync(h->params.p, fam_delta, (size_t)sumG * 8, hipMemcpyHostToDevice, h->stream),
+           "list upload");
+    a.delta = (const double *)h->params.p;
     a.depth_c = depth_c;
     a.normal_c = normal_c;
     a.dbar = dbar;

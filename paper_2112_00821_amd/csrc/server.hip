@@ -2,9 +2,10 @@
 // arrive, each matched against its stream's previous keyframes (the
 // sliding bundle of the online-mapping use; keyframe when the camera moved
 // at least min_baseline since the last keyframe), admitted into one of
-// n_slots pipeline slots when a slot is free and the frame's device-memory
-// footprint fits the budget, and run concurrently (each slot is a handle
-// with its own HIP stream, so frames overlap on the device).
+// n_slots pipeline slots when a slot is free and the device memory the
+// slots hold, plus what the chosen slot must grow by for the frame, fits the
+// budget, and run concurrently (each slot is a handle with its own HIP
+// stream, so frames overlap on the device).
 //
 // Host code over the library's public C ABI.  A worker thread admits
 // queued frames and collects finished ones; submit and result calls only
@@ -27,6 +28,12 @@
 #include <vector>
 
 #include "../../include/fassmvs.h"
+#include "handle_internal.hpp"
+
+using fmvs::handle_growth;
+using fmvs::handle_held;
+using fmvs::handle_set_exact_growth;
+using fmvs::handle_trim;
 
 namespace {
 
@@ -70,6 +77,9 @@ struct Stream {
     double K[9];
     int w = 0, h = 0;
     std::vector<fassmvs_plane_family> fams;
+    // copies of the families' explicit plane lists (fams[f].delta points
+    // into them); shared so that a frame being submitted keeps them alive
+    std::shared_ptr<const std::vector<std::vector<double>>> lists;
     int max_kf = 4;
     double min_baseline = 1.0;
     // keyframes, most recent first: image and pose
@@ -157,7 +167,7 @@ struct Slot {
 
 struct fassmvs_server {
     fassmvs_config cfg;
-    uint64_t budget = 0, in_use = 0;
+    uint64_t budget = 0;
     std::vector<Slot> slots;
     std::map<int, std::unique_ptr<Stream>> streams;
     Pools pools;
@@ -187,21 +197,79 @@ void camera_centre(const double *R, const double *t, double *C) {
     for (int i = 0; i < 3; ++i) C[i] = -(R[i] * t[0] + R[3 + i] * t[1] + R[6 + i] * t[2]);
 }
 
-// Admit the head of the queue into a free slot if its footprint fits.
+// The frame's bundle as the pipeline takes it: the reference image and its
+// stream's keyframes (all earlier in the sequence: left side).
+int bundle_of(const Request &req, const Stream &st, fassmvs_image &ref, fassmvs_image *views, int8_t *side) {
+    std::memset(&ref, 0, sizeof(ref));
+    ref.pixels = req.img->b.p;
+    ref.width = st.w;
+    ref.height = st.h;
+    ref.stride = st.w;
+    std::memcpy(ref.R, req.R, sizeof(ref.R));
+    std::memcpy(ref.t, req.t, sizeof(ref.t));
+    const int nv = (int)req.views.size();
+    for (int k = 0; k < nv; ++k) {
+        std::memset(&views[k], 0, sizeof(views[k]));
+        views[k].pixels = req.views[k].img->b.p;
+        views[k].width = st.w;
+        views[k].height = st.h;
+        views[k].stride = st.w;
+        std::memcpy(views[k].R, req.views[k].R, sizeof(views[k].R));
+        std::memcpy(views[k].t, req.views[k].t, sizeof(views[k].t));
+        side[k] = -1;
+    }
+    return nv;
+}
+
+// Admit the head of the queue into a free slot if the device memory allows.
+// The account is the memory the slots' pipelines actually hold (their
+// buffers only grow, exactly to what a frame needs) plus the growth the
+// frame needs on the chosen slot (the free slot that needs the least).  A
+// slot grows only while no frame is in flight, so its reallocation never
+// waits on other frames; when the budget is short and the device is idle,
+// the other idle slots' buffers are released first, then the chosen one's.
 // Called by the worker (which alone touches the slots) with lk held; the
 // lock is released while the frame is enqueued.  Returns true if a request
 // left the queue.
 bool admit_one(fassmvs_server *s, std::unique_lock<std::mutex> &lk) {
     if (s->queue.empty()) return false;
-    Slot *free_slot = nullptr;
-    for (auto &sl : s->slots)
-        if (!sl.busy) {
-            free_slot = &sl;
-            break;
-        }
-    if (!free_slot) return false;
     Request &head = s->queue.front();
-    if (s->in_flight > 0 && s->in_use + head.footprint > s->budget) return false;
+    Stream &hs = *s->streams.at(head.stream);
+    Slot *free_slot = nullptr;
+    uint64_t grow = 0;
+    if (!head.views.empty()) {
+        fassmvs_image ref, views[FASSMVS_MAX_VIEWS];
+        int8_t side[FASSMVS_MAX_VIEWS];
+        const int nv = bundle_of(head, hs, ref, views, side);
+        for (auto &sl : s->slots) {
+            if (sl.busy) continue;
+            uint64_t g = 0;
+            if (handle_growth(sl.h, &ref, views, side, nv, hs.K, hs.fams.data(), (int32_t)hs.fams.size(), &g) !=
+                FASSMVS_OK)
+                g = 0;   // the submit reports the frame's error
+            if (!free_slot || g < grow) {
+                free_slot = &sl;
+                grow = g;
+            }
+        }
+        if (!free_slot) return false;
+        if (grow > 0 && s->in_flight > 0) return false;
+        uint64_t held = 0;
+        for (auto &sl : s->slots) held += handle_held(sl.h);
+        if (held + grow > s->budget) {
+            if (s->in_flight > 0) return false;
+            for (auto &sl : s->slots)
+                if (&sl != free_slot) handle_trim(sl.h);
+            held = 0;
+            for (auto &sl : s->slots) held += handle_held(sl.h);
+            if (held + grow > s->budget) {
+                handle_trim(free_slot->h);
+                if (handle_growth(free_slot->h, &ref, views, side, nv, hs.K, hs.fams.data(),
+                                  (int32_t)hs.fams.size(), &grow) != FASSMVS_OK)
+                    grow = 0;
+            }
+        }
+    }
     Request req = std::move(head);
     s->queue.pop_front();
     Stream &st = *s->streams.at(req.stream);
@@ -229,36 +297,17 @@ bool admit_one(fassmvs_server *s, std::unique_lock<std::mutex> &lk) {
     }
     // reserve before enqueueing (the lock is dropped meanwhile)
     free_slot->busy = true;
-    s->in_use += req.footprint;
     s->in_flight++;
     const double K[9] = {st.K[0], st.K[1], st.K[2], st.K[3], st.K[4], st.K[5], st.K[6], st.K[7], st.K[8]};
     const std::vector<fassmvs_plane_family> fams = st.fams;
-    const int w = st.w, h = st.h;
+    const auto lists = st.lists;
+    fassmvs_image ref, views[FASSMVS_MAX_VIEWS];
+    int8_t side[FASSMVS_MAX_VIEWS];
+    const int nv = bundle_of(req, st, ref, views, side);
     lk.unlock();
     // the slot's stream waits (on the device) for the images' uploads
     hipStreamWaitEvent(free_slot->stream, req.img->b.ready, 0);
     for (auto &v : req.views) hipStreamWaitEvent(free_slot->stream, v.img->b.ready, 0);
-    fassmvs_image ref;
-    std::memset(&ref, 0, sizeof(ref));
-    ref.pixels = req.img->b.p;
-    ref.width = w;
-    ref.height = h;
-    ref.stride = w;
-    std::memcpy(ref.R, req.R, sizeof(ref.R));
-    std::memcpy(ref.t, req.t, sizeof(ref.t));
-    fassmvs_image views[FASSMVS_MAX_VIEWS];
-    int8_t side[FASSMVS_MAX_VIEWS];
-    const int nv = (int)req.views.size();
-    for (int k = 0; k < nv; ++k) {
-        std::memset(&views[k], 0, sizeof(views[k]));
-        views[k].pixels = req.views[k].img->b.p;
-        views[k].width = w;
-        views[k].height = h;
-        views[k].stride = w;
-        std::memcpy(views[k].R, req.views[k].R, sizeof(views[k].R));
-        std::memcpy(views[k].t, req.views[k].t, sizeof(views[k].t));
-        side[k] = -1;   // earlier in the sequence: one-sided bundle
-    }
     uint64_t ticket = 0;
     fassmvs_status rc = fassmvs_submit_frame(free_slot->h, &ref, views, side, nv, K, fams.data(),
                                              (int32_t)fams.size(), FASSMVS_MEM_DEVICE, &ticket);
@@ -268,7 +317,6 @@ bool admit_one(fassmvs_server *s, std::unique_lock<std::mutex> &lk) {
         res.info.status = rc;
         res.info.latency_ms = ms_since(req.arrival, Clock::now());
         free_slot->busy = false;
-        s->in_use -= req.footprint;
         s->in_flight--;
         s->done.push_back(res);
         s->cv_done.notify_all();
@@ -298,7 +346,6 @@ bool collect(fassmvs_server *s, std::unique_lock<std::mutex> &lk) {
         res.info.status = rc;
         res.info.latency_ms = ms_since(finished.arrival, now);
         if (rc != FASSMVS_OK) give_maps(res);
-        s->in_use -= finished.footprint;
         s->in_flight--;
         sl.busy = false;
         sl.ticket = 0;
@@ -356,7 +403,9 @@ fassmvs_status fassmvs_server_create(const fassmvs_config *cfg, int32_t n_slots,
         fassmvs_config c = *cfg;
         c.stream = sl.stream;
         c.keep_levels = 0;
+        c.hbm_budget_bytes = hbm_budget_bytes;
         fassmvs_status st = fassmvs_create(&c, &sl.h);
+        if (st == FASSMVS_OK) handle_set_exact_growth(sl.h);
         if (st != FASSMVS_OK) {
             for (auto &o : s->slots) {
                 if (o.h) fassmvs_destroy(o.h);
@@ -382,6 +431,15 @@ fassmvs_status fassmvs_server_open_stream(fassmvs_server *s, const double K[9], 
     st->w = width;
     st->h = height;
     st->fams.assign(families, families + n_families);
+    auto lists = std::make_shared<std::vector<std::vector<double>>>(n_families);
+    for (int f = 0; f < n_families; ++f) {
+        if (!families[f].delta) continue;
+        if (families[f].count < 2 || families[f].count > FASSMVS_MAX_TOP_PLANES)
+            return sfail(s, FASSMVS_EINVAL, "an explicit plane list needs 2..256 distances");
+        (*lists)[f].assign(families[f].delta, families[f].delta + families[f].count);
+        st->fams[f].delta = (*lists)[f].data();
+    }
+    st->lists = lists;
     st->max_kf = max_keyframes;
     st->min_baseline = min_baseline;
     st->pools = &s->pools;

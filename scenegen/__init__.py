@@ -581,6 +581,10 @@ WORKLOADS = {
     **{f"config4_{sd}": (lambda sd=sd: config4_frame(sd)) for sd in CONFIG4_SEEDS},
     "config1_xr": lambda: with_cross_ratio_counts(config1(0)),
     "config2_small_xr": lambda: with_cross_ratio_counts(config2(1, 320, 184, planes=32, window=32)),
+    # an explicit list of varying spacing (geometric distances over the range)
+    "config2_small_list": lambda: with_geometric_lists(config2(1, 320, 184, planes=32, window=32)),
+    # slanted families given by the depth range only (bounding planes)
+    "config3_small_range": lambda: with_depth_range(config3(2, 320, 180, planes=16, window=16), 20.0, 400.0),
 }
 
 
@@ -607,6 +611,27 @@ def with_cross_ratio_counts(wl):
     """The same bundle with every family's coarsest plane count left to the
     cross-ratio construction (count 0)."""
     return dict(wl, families=[dict(f, count=0) for f in wl["families"]])
+
+
+def with_geometric_lists(wl):
+    """The same bundle with every family's coarsest list given explicitly:
+    count distances in geometric progression over [delta_min, delta_max]
+    (denser in distance near the camera, sparser in inverse distance there
+    than a list uniform in inverse distance)."""
+    fams = []
+    for f in wl["families"]:
+        n = int(f["count"])
+        d = f["delta_min"] * (f["delta_max"] / f["delta_min"]) ** (np.arange(n) / (n - 1))
+        fams.append(dict(n=f["n"], delta=[float(x) for x in d], count=n))
+    return dict(wl, families=fams)
+
+
+def with_depth_range(wl, depth_min: float, depth_max: float):
+    """The same bundle with every family's distance range left to the
+    bounding planes of the depth range (delta_min = delta_max = 0)."""
+    fams = [dict(n=f["n"], delta_min=0.0, delta_max=0.0, depth_min=depth_min, depth_max=depth_max,
+                 count=f["count"]) for f in wl["families"]]
+    return dict(wl, families=fams)
 
 
 def with_sgm_variant(wl, variant: int):

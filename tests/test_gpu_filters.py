@@ -88,8 +88,8 @@ def test_geometric_filter_matches_oracle(orc, hd, noise):
     hits_e, keep_e = orc.geo_consistency(K, deps[ref], [deps[k] for k in nb], Rr, tr, 10.0, 3)
     dref = hd.upload(deps[ref])
     hits, keep = hd.filter_geometric(K, dref, [hd.upload(deps[k]) for k in nb], Rr, tr, 10.0, 3)
-    assert np.mean(hits.numpy() == hits_e) >= 0.9999
-    assert np.mean(keep.numpy() == keep_e) >= 0.9999
+    assert np.array_equal(hits.numpy(), hits_e), np.mean(hits.numpy() == hits_e)
+    assert np.array_equal(keep.numpy(), keep_e), np.mean(keep.numpy() == keep_e)
     assert np.array_equal(dref.numpy() > 0, keep.numpy().astype(bool))
     if noise == 0.0:
         assert keep_e.mean() > 0.5

@@ -11,20 +11,24 @@ Checked:
 
 * pyramid (all images, all levels) and the level-0 reference census:
   bit-exact over the whole frame;
-* the coarsest level: every map compared with the oracle's own full run of
-  that level (labels >= 99.9 %, depth 1e-3), and the level-1 seeds derived
-  from it (1920x1080 only: the oracle's run of the 676x380 x 384-label level
-  is replaced there by sampled costs);
-* level 0: the cost volume at sampled pixels (all labels of the pixel) and
-  the path costs along sampled whole paths (a row, a column, diagonals), the
-  oracle recomputing the costs of every pixel on the path itself.  The label
-  window of each sampled pixel is the one the GPU pipeline chose; the windows
-  are checked separately to be centred on the GPU's seed depth.
+* 1920x1080 census: every level of the frame against the oracle's own full
+  run (started in a process of its own when the session starts): labels
+  >= 99.9 %, depth 1e-3 relative, normals and confidence 1e-4 where the
+  depth stencil agrees, windows and surface-normal offsets, and the whole
+  level-0 cost volume where the windows agree;
+* 2704x1520: the coarsest level (676x380 x 384 labels) against the oracle's
+  run of that level, with the seeds it gives the next level;
+* level 0 of every workload: the cost volume at sampled pixels (all labels
+  of the pixel) and the path costs along sampled whole paths (a row, a
+  column, diagonals) -- the oracle's recursion run on the pipeline's own
+  cost volume along the path must give the same path costs everywhere, and
+  the pipeline's costs on the path are compared with the oracle's.
 """
 import numpy as np
 import pytest
 
 import scenegen
+from parity_util import compare_level, first_mismatch
 
 pytestmark = pytest.mark.gpu
 
@@ -103,25 +107,68 @@ def _level(orc, wl, level):
     return Ki, plan, H
 
 
-def test_coarsest_level(orc, run):
+def _maps(h, level, n_fam):
+    return dict(label=h.level_map(level, 4), depth=h.level_map(level, 0), normal=h.level_map(level, 2),
+                conf=h.level_map(level, 3))
+
+
+def _oracle_maps(z, level):
+    return dict(label=z[f"l{level}_label"], depth=z[f"l{level}_depth"], normal=z[f"l{level}_normal"],
+                conf=z[f"l{level}_conf"])
+
+
+@pytest.mark.timeout(900)
+def test_whole_frame_against_oracle_run(orc, run, oracle_run):
+    """config2: every level of the frame, and the returned level-0 maps,
+    against the oracle's full run of the same bundle."""
+    name, wl, h, d = run
+    if name != "config2":
+        pytest.skip("the oracle's whole-frame run is made for the 1920x1080 census workload")
+    z = oracle_run("config2")
+    n = wl["params"]["n_levels"]
+    nf = len(wl["families"])
+    for l in range(n - 1, -1, -1):
+        rep = compare_level(_maps(h, l, nf), _oracle_maps(z, l))
+        print(f"[fullsize] config2 level {l}: {rep}", flush=True)
+        if l < n - 1:
+            offs = h.level_map(l, 6, n_fam=nf)
+            dI = h.level_map(l, 7, n_fam=nf)
+            mo, md = np.mean(offs == z[f"l{l}_offs"]), np.mean(dI == z[f"l{l}_dI"])
+            print(f"[fullsize] config2 level {l}: windows {mo:.6f}, surface-normal offsets {md:.6f}", flush=True)
+            assert mo >= 0.999 and md >= 0.999
+    ok = z["l0_depth"] > 0
+    agree = h.level_map(0, 4) == z["l0_label"]
+    sel = ok & agree
+    assert np.max(np.abs(d[sel] - z["l0_depth"][sel]) / z["l0_depth"][sel]) <= 1e-3
+    # the whole level-0 cost volume where the pixel's windows agree
+    D = sum(orc.level_plan(wl, 0)["W"])
+    S = h.level_map(0, 9, D=D)
+    same_win = np.all(h.level_map(0, 6, n_fam=nf) == z["l0_offs"], axis=0)
+    eq = S[same_win] == z["l0_S"][same_win]
+    frac = eq.mean()
+    fm_ = first_mismatch(S[same_win], z["l0_S"][same_win])
+    print(f"[fullsize] config2 level-0 cost volume: {frac:.8f} of {eq.size} entries identical "
+          f"(windows agree on {same_win.mean():.6f} of the pixels); first difference {fm_}", flush=True)
+    assert frac >= 0.9999
+    assert np.max(np.abs(S[same_win].astype(int) - z["l0_S"][same_win].astype(int))) <= 4
+
+
+@pytest.mark.timeout(900)
+def test_coarsest_level(orc, run, oracle_run):
     name, wl, h, _ = run
     top = wl["params"]["n_levels"] - 1
-    if name == "config2":
-        out = orc.run_frame(wl, keep=True, levels_only=top)
-        lv = out["levels"][top]
-        lab = h.level_map(top, 4)
-        agree = lab == lv["label"]
-        assert agree.mean() >= 0.999, agree.mean()
-        dep = h.level_map(top, 0)
-        ok = agree & (lv["depth"] > 0)
-        assert np.max(np.abs(dep[ok] - lv["depth"][ok]) / lv["depth"][ok]) <= 1e-3
-        if np.array_equal(dep, lv["depth"]):
-            assert np.max(np.abs(h.level_map(top, 2) - lv["normal"])) <= 1e-4
-            assert np.max(np.abs(h.level_map(top, 3) - lv["conf"])) <= 1e-4
-            # seeds of the next level from the same maps
-            seed = lv["seed"]
-            assert np.mean(h.level_map(top - 1, 6) == seed["offs"]) >= 0.9999
-            assert np.mean(h.level_map(top - 1, 7) == seed["dI"]) >= 0.9999
+    nf = len(wl["families"])
+    if name in ("config2", "config3"):
+        z = oracle_run(name)
+        rep = compare_level(_maps(h, top, nf), _oracle_maps(z, top))
+        print(f"[fullsize] {name} coarsest level: {rep}", flush=True)
+        # seeds of the next level from the coarsest maps
+        so = z[f"l{top}_seed_offs"] if f"l{top}_seed_offs" in z else z[f"l{top - 1}_offs"]
+        sd = z[f"l{top}_seed_dI"] if f"l{top}_seed_dI" in z else z[f"l{top - 1}_dI"]
+        mo = np.mean(h.level_map(top - 1, 6, n_fam=nf) == so)
+        md = np.mean(h.level_map(top - 1, 7, n_fam=nf) == sd)
+        print(f"[fullsize] {name} seeds of level {top - 1}: windows {mo:.6f}, offsets {md:.6f}", flush=True)
+        assert mo >= 0.999 and md >= 0.999
         return
     # sampled costs of the coarsest level over every family's full list (the
     # pipeline keeps only level 0's census and volume, so the stage entry
@@ -144,7 +191,7 @@ def test_coarsest_level(orc, run):
     xy = np.concatenate([xy, [[0, 0], [ww - 1, hh - 1], [ww - 1, 0], [0, hh - 1]]]).astype(np.int32)
     exp = _cost_pixels(orc, wl, img, views, plan, H, xy)
     got = S[xy[:, 1], xy[:, 0]]
-    assert np.array_equal(got, exp), np.mean(got == exp)
+    assert np.array_equal(got, exp), first_mismatch(got, exp)
 
 
 def test_level0_windows_centred_on_seed(orc, run):
@@ -154,8 +201,8 @@ def test_level0_windows_centred_on_seed(orc, run):
     d1 = h.level_map(1, 0)
     hh, ww = offs.shape[1:]
     dbar = orc.upsample_nn(d1, ww, hh)
-    exp = orc.window_offsets(dbar, Ki, plan["fam_n"], plan["inv_dmin"], plan["step"], plan["G"], plan["W"])
-    assert np.array_equal(offs, exp)
+    exp = orc.window_offsets(dbar, Ki, plan["fam_n"], plan["deltas"], plan["W"])
+    assert np.array_equal(offs, exp), first_mismatch(offs, exp)
 
 
 def test_level0_cost_samples(orc, run):
@@ -171,9 +218,14 @@ def test_level0_cost_samples(orc, run):
     xy = np.concatenate([xy, [[0, 0], [ww - 1, hh - 1], [ww - 1, 0], [0, hh - 1]]])
     exp = _cost_pixels(orc, wl, wl["ref"]["img"], [v["img"] for v in wl["views"]], plan, H, xy, offs=offs)
     got = S[xy[:, 1], xy[:, 0]]
-    # the pipeline's own homographies (computed apart from the oracle's) may
-    # differ in the last bit, which can flip a census bit of a rare sample
-    assert np.mean(got == exp) >= 0.9999
+    # the pipeline computes its homographies itself (H = A + B / delta per
+    # plane family), so a warped sample can differ from the oracle's in its
+    # last bit and flip the census bit of a near-tie: the first such entry is
+    # printed, the gate counts them
+    frac = np.mean(got == exp)
+    print(f"[fullsize] level-0 cost samples: {frac:.6f} identical; first difference {first_mismatch(got, exp)}",
+          flush=True)
+    assert frac >= 0.9999
     assert np.max(np.abs(got.astype(int) - exp.astype(int))) <= 2
 
 
@@ -213,7 +265,6 @@ def test_level0_path_costs(orc, run, r, which):
     dI = h.level_map(0, 7, n_fam=nf)
     Sp = _cost_pixels(orc, wl, wl["ref"]["img"], [v["img"] for v in wl["views"]], plan, H, xy, offs=offs)
     n = len(xy)
-    strip_S = Sp.reshape(n, 1, D)
     strip_offs = offs[:, xy[:, 1], xy[:, 0]].reshape(nf, n, 1)
     strip_dI = np.zeros((8, n, 1, nf), np.int8)
     strip_dI[2] = dI[r, xy[:, 1], xy[:, 0], :].reshape(n, 1, nf)
@@ -221,13 +272,16 @@ def test_level0_path_costs(orc, run, r, which):
     m = 1 if _ncc(wl) else orc.subset_multiplier(wl["side"])
     p = wl["params"]
     lut = orc.p2_lut(m * p["p1"], p["p2_mode"], m * p["p2_fixed"], p["p2_alpha"], p["p2_beta"])
-    _, Lr = orc.sgm(strip_S, plan["W"], m * p["p1"], lut, ref, 4, offs=strip_offs, dI=strip_dI,
+    exp_S = Sp.reshape(n, D)
+    # the pipeline's own costs on the path, compared with the oracle's
+    S_gpu = h.level_map(0, 9, D=D)[xy[:, 1], xy[:, 0]]
+    frac = np.mean(S_gpu == exp_S)
+    print(f"[fullsize] path r={r}: costs identical on {frac:.6f}; first difference {first_mismatch(S_gpu, exp_S)}",
+          flush=True)
+    assert frac >= 0.999
+    # the recursion on the pipeline's own costs: every path cost of the path
+    _, Lr = orc.sgm(S_gpu.reshape(n, 1, D), plan["W"], m * p["p1"], lut, ref, 4, offs=strip_offs, dI=strip_dI,
                     want_sbar=False, want_lr=True)
     exp = Lr[2, :, 0, :]                      # the strip's downward path
     got = h.level_map(0, 10 + r, D=D)[xy[:, 1], xy[:, 0]]
-    # S on the path is recomputed independently; where the GPU's S differs
-    # (rare last-bit warp differences) the recursion diverges from there on
-    S_gpu = h.level_map(0, 9, D=D)[xy[:, 1], xy[:, 0]]
-    first_diff = np.argmax(np.any(S_gpu != Sp, axis=1)) if np.any(S_gpu != Sp) else n
-    assert first_diff >= 0.9 * n
-    assert np.array_equal(got[:first_diff], exp[:first_diff])
+    assert np.array_equal(got, exp), first_mismatch(got, exp)

@@ -134,6 +134,44 @@ def test_footprint_admission_serialises_under_a_tight_budget(fm, streams):
         assert np.array_equal(got[f]["depth"], ref[(0, f)][1]["depth"])
 
 
+def test_admission_counts_held_memory_with_mixed_frame_sizes(fm, streams):
+    """Two stream sizes on three slots under a budget just above one large
+    frame's footprint: admission counts what the slots' pipelines hold (a
+    slot that ran a large frame keeps its buffers) plus the growth a frame
+    needs, so no frame fails for memory, and the maps are those of a run
+    without a budget."""
+    import ctypes as C
+    big, small = streams[1], streams[2]
+    cfg = _cfg(fm, big)
+    fams = fm._families(big["families"])
+    fp = C.c_uint64()
+    assert fm.lib().fassmvs_frame_footprint(C.byref(cfg), big["width"], big["height"], 4, fams, 1,
+                                            C.byref(fp)) == fm.OK
+    order = []
+    for f in range(5):
+        order += [(0, f), (1, f)]
+    pair = [big, small]
+    ref = _run(fm, pair, order, 3, cfg)
+    out = {}
+    with fm.Server(cfg, n_slots=3, hbm_budget_bytes=fp.value + 1) as srv:
+        sid = {i: srv.open_stream(st["K"], st["width"], st["height"], st["families"]) for i, st in enumerate(pair)}
+        rid = {}
+        for s, f in order:
+            rid[srv.submit(sid[s], *pair[s]["frames"][f])] = (s, f)
+        for _ in range(len(order)):
+            r = srv.next(-1)
+            out[rid[r["request_id"]]] = (r, srv.fetch(r["request_id"], r["width"], r["height"])
+                                         if r["status"] == fm.OK else None)
+    for key, (r, maps) in out.items():
+        r0, m0 = ref[key]
+        assert r["status"] == r0["status"], (key, r["status"])
+        assert r["status"] in (fm.OK, fm.ENOTFOUND)
+        if maps is not None:
+            for k in ("depth", "normal", "conf"):
+                assert np.array_equal(maps[k], m0[k]), (key, k)
+    assert sum(r["status"] == fm.OK for r, _ in out.values()) == 8
+
+
 def test_server_errors(fm, streams):
     st = streams[0]
     cfg = _cfg(fm, st)

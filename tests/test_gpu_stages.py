@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import scenegen
+from parity_util import first_mismatch
 
 pytestmark = pytest.mark.gpu
 
@@ -225,12 +226,34 @@ def test_seed_bit_exact(orc, hd):
     Ki_f, _ = orc.kinv_level(np.asarray(wl["K"]), 1)
     fh, fw = out["levels"][1]["img"].shape
     dbar, nbar, offs, dI = hd.stage_seed(hd.upload(coarse["depth"]), hd.upload(coarse["normal"]), fw, fh, Ki_f,
-                                         plan_f["fam_n"], plan_f["inv_dmin"], plan_f["step"], plan_f["G"],
-                                         plan_f["W"])
+                                         plan_f["fam_n"], plan_f["deltas"], plan_f["W"])
     assert np.array_equal(dbar.numpy(), seed["dbar"])
     assert np.array_equal(nbar.numpy(), seed["nbar"])
-    assert np.array_equal(offs.numpy(), seed["offs"])
-    assert np.mean(dI.numpy() == seed["dI"]) >= 0.9999
+    assert np.array_equal(offs.numpy(), seed["offs"]), first_mismatch(offs.numpy(), seed["offs"])
+    assert np.array_equal(dI.numpy(), seed["dI"]), first_mismatch(dI.numpy(), seed["dI"])
+
+
+@pytest.mark.parametrize("name", ["config2_small_list", "config2_small_xr"])
+def test_seed_bit_exact_on_lists_of_varying_spacing(orc, hd, name):
+    """Windows and surface-normal offsets from plane lists that are not
+    uniform in inverse distance (an explicit geometric list; the cross-ratio
+    list): the continuous index is found by bisection on the GPU and by a
+    scan in the oracle."""
+    wl = scenegen.make_workload(name)
+    out = orc.run_frame(wl, keep=True, levels_only=1)
+    top = wl["params"]["n_levels"] - 1
+    coarse = out["levels"][top]
+    seed = coarse["seed"]
+    plan_f = orc.level_plan(wl, top - 1)
+    Ki_f, _ = orc.kinv_level(np.asarray(wl["K"]), top - 1)
+    fh, fw = out["levels"][top - 1]["img"].shape
+    inv = [1.0 / d for d in plan_f["deltas"]]
+    assert any(np.ptp(np.diff(i)) > 1e-3 * abs(np.mean(np.diff(i))) for i in inv)   # really non-uniform
+    dbar, nbar, offs, dI = hd.stage_seed(hd.upload(coarse["depth"]), hd.upload(coarse["normal"]), fw, fh, Ki_f,
+                                         plan_f["fam_n"], plan_f["deltas"], plan_f["W"])
+    assert np.array_equal(offs.numpy(), seed["offs"]), first_mismatch(offs.numpy(), seed["offs"])
+    assert np.array_equal(dI.numpy(), seed["dI"]), first_mismatch(dI.numpy(), seed["dI"])
+    assert np.count_nonzero(seed["dI"]) > 0
 
 
 @pytest.mark.parametrize("kernel", ["packed", "one-label"])

@@ -231,3 +231,63 @@ def test_census_hamming_metric(orc):
     # inverted intensities flip every bit that is not a tie
     ci = orc.census(-a, 9, 7)
     assert np.all(pc(ca ^ ci)[3:-3, 4:-4] == 62)
+
+
+def _bilinear_f64(img, H, rw, rh):
+    """Plain float64 bilinear clamp-to-edge warp written with numpy (no
+    fused operations, no float32 rounding): the value at reference pixel q is
+    the view sampled at H (q + 0.5) / hz - 0.5; a point behind the view's
+    focal plane reads the top-left pixel."""
+    h, w = img.shape
+    I = img.astype(np.float64)
+    yy, xx = np.mgrid[0:rh, 0:rw]
+    q = np.stack([xx + 0.5, yy + 0.5, np.ones_like(xx, dtype=np.float64)], -1)
+    p = q @ np.asarray(H, np.float64).T
+    front = p[..., 2] > 1e-300
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sx = np.where(front, p[..., 0] / p[..., 2], 0.0) - 0.5
+        sy = np.where(front, p[..., 1] / p[..., 2], 0.0) - 0.5
+    sx = np.clip(sx, -1.0, float(w))
+    sy = np.clip(sy, -1.0, float(h))
+    x0 = np.floor(sx)
+    y0 = np.floor(sy)
+    ax, ay = sx - x0, sy - y0
+    x0 = x0.astype(int)
+    y0 = y0.astype(int)
+    xa, xb = np.clip(x0, 0, w - 1), np.clip(x0 + 1, 0, w - 1)
+    ya, yb = np.clip(y0, 0, h - 1), np.clip(y0 + 1, 0, h - 1)
+    top = I[ya, xa] * (1 - ax) + I[ya, xb] * ax
+    bot = I[yb, xa] * (1 - ax) + I[yb, xb] * ax
+    return top * (1 - ay) + bot * ay
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_warp_within_1e4_of_float64_bilinear(orc, seed):
+    """The oracle's fixed warp (double coordinates, float interpolation)
+    stays within 1e-4 (on the [0, 1] intensity scale) of a plain float64
+    bilinear warp, on random images and random projective homographies
+    that shrink, stretch, shear and move the view partly outside the
+    image."""
+    rng = np.random.default_rng(300 + seed)
+    h, w = int(rng.integers(20, 90)), int(rng.integers(20, 120))
+    img = rng.integers(0, 256, (h, w)).astype(np.uint8)
+    A = np.eye(3)
+    A[:2, :2] += rng.normal(0, 0.25, (2, 2))
+    A[:2, 2] = rng.uniform(-0.3, 0.3, 2) * [w, h]
+    A[2, :2] = rng.normal(0, 2e-3, 2)
+    got = orc.warp(img, A, w, h)
+    exp = _bilinear_f64(img, A, w, h)
+    assert np.max(np.abs(got - exp)) / 255.0 <= 1e-4, np.max(np.abs(got - exp)) / 255.0
+
+
+def test_warp_float64_behind_and_far_outside(orc):
+    """Points behind the view and far outside: the same value as the float64
+    definition (border pixels)."""
+    rng = np.random.default_rng(8)
+    img = rng.integers(0, 256, (30, 40)).astype(np.uint8)
+    for H in (np.diag([1.0, 1.0, -1.0]), np.array([[1, 0, 1e9], [0, 1, -1e9], [0, 0, 1.0]]),
+              np.array([[1, 0, -1e7], [0, 1, 1e7], [0, 0, 1.0]]),
+              np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.02, 0.0, -0.3]])):
+        got = orc.warp(img, H, 40, 30)
+        exp = _bilinear_f64(img, H, 40, 30)
+        assert np.max(np.abs(got - exp)) / 255.0 <= 1e-4

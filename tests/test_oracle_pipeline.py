@@ -96,7 +96,8 @@ def test_windows_cover_truth(orc):
     plan = orc.level_plan(wl, 0)
     gt = wl["gt"]["depth"]
     inv = 1.0 / gt
-    j = (plan["inv_dmin"][0] - inv) / plan["step"][0]
+    dl = plan["deltas"][0]
+    j = np.interp(inv, (1.0 / dl)[::-1], np.arange(len(dl), dtype=np.float64)[::-1])
     o = seed["offs"][0]
     inside = (j >= o - 0.5) & (j <= o + plan["W"][0] - 0.5)
     assert inside.mean() > 0.9, inside.mean()

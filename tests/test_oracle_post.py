@@ -151,19 +151,26 @@ def test_window_offsets_centre_on_seed(orc):
     Ki, _ = orc.kinv_level(K, 0)
     G, W = 64, 16
     deltas = orc.plane_list(20.0, 400.0, G)
-    step = (1 / 20 - 1 / 400) / (G - 1)
     rng = np.random.default_rng(4)
     j = rng.integers(0, G, (30, 40))
     dbar = deltas[j].astype(np.float32)
-    offs = orc.window_offsets(dbar, Ki, np.array([[0, 0, -1.0]]), np.array([1 / 20]), np.array([step]), [G], [W])
+    offs = orc.window_offsets(dbar, Ki, np.array([[0, 0, -1.0]]), [deltas], [W])
     exp = np.clip(j - W // 2, 0, G - W)
     assert np.array_equal(offs[0], exp)
     dbar[0, 0] = 0
-    offs = orc.window_offsets(dbar, Ki, np.array([[0, 0, -1.0]]), np.array([1 / 20]), np.array([step]), [G], [W])
+    offs = orc.window_offsets(dbar, Ki, np.array([[0, 0, -1.0]]), [deltas], [W])
     assert offs[0, 0, 0] == (G - W) // 2
     # a window covering the whole list starts at 0
-    offs = orc.window_offsets(dbar, Ki, np.array([[0, 0, -1.0]]), np.array([1 / 20]), np.array([step]), [G], [G])
+    offs = orc.window_offsets(dbar, Ki, np.array([[0, 0, -1.0]]), [deltas], [G])
     assert offs.max() == 0
+    # a list of varying spacing (geometric distances): the window of a seed on
+    # plane j still starts at j - W/2
+    geo = 20.0 * 1.05 ** np.arange(G)
+    dbar = geo[j].astype(np.float32)
+    offs = orc.window_offsets(dbar, Ki, np.array([[0, 0, -1.0]]), [geo], [W])
+    j32 = np.array([np.abs(geo - v).argmin() for v in dbar.astype(np.float64).ravel()]).reshape(j.shape)
+    assert np.array_equal(j32, j)
+    assert np.array_equal(offs[0], np.clip(j - W // 2, 0, G - W))
 
 
 def test_delta_i_on_an_analytic_plane(orc):
@@ -177,8 +184,9 @@ def test_delta_i_on_an_analytic_plane(orc):
     c = 40.0
     d, _ = _plane_depth(Ki, n, c, 80, 60)
     step = (1 / 20 - 1 / 400) / 511
+    deltas = orc.plane_list(20.0, 400.0, 512)
     nb = np.broadcast_to(n, (60, 80, 3)).astype(np.float32).copy()
-    dI = orc.delta_i(d.astype(np.float32), nb, Ki, np.array([[0, 0, -1.0]]), np.array([step]))
+    dI = orc.delta_i(d.astype(np.float32), nb, Ki, np.array([[0, 0, -1.0]]), [deltas])
     DIRS = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1)]
     for r, (dx, dy) in enumerate(DIRS):
         # 1/d(p) - 1/d(q) = -(n^T K^-1 (p - q)) / c with p - q = r
@@ -188,5 +196,94 @@ def test_delta_i_on_an_analytic_plane(orc):
         assert np.mean(got == exp) > 0.999, (r, v, np.unique(got))
     assert np.array_equal(dI[2], -dI[3])
     assert np.all(dI[0] == 0)                     # plane constant along x: no jump
-    z = orc.delta_i(np.zeros((4, 5), np.float32), nb[:4, :5], Ki, np.array([[0, 0, -1.0]]), np.array([step]))
+    z = orc.delta_i(np.zeros((4, 5), np.float32), nb[:4, :5], Ki, np.array([[0, 0, -1.0]]), [deltas])
     assert not z.any()
+
+
+def _index_interp(deltas, iv):
+    """Continuous index of inverse distances iv in a list of increasing
+    distances, by numpy's piecewise-linear interpolation, extended linearly
+    beyond the ends (independent of the oracle's scan)."""
+    inv = 1.0 / np.asarray(deltas, np.float64)
+    idx = np.arange(len(inv), dtype=np.float64)
+    iv = np.asarray(iv, np.float64)
+    j = np.interp(iv, inv[::-1], idx[::-1])
+    lo = iv > inv[0]
+    j = np.where(lo, (inv[0] - iv) / (inv[0] - inv[1]), j)
+    hi = iv < inv[-1]
+    G = len(inv)
+    j = np.where(hi, G - 2 + (inv[-2] - iv) / (inv[-2] - inv[-1]), j)
+    return j
+
+
+def test_list_index_pins(orc):
+    """The continuous plane index: exact at every plane, affine in inverse
+    distance for a list uniform in it, and numpy's piecewise-linear
+    interpolation (extended past the ends) for a list of varying spacing."""
+    uni = orc.plane_list(20.0, 400.0, 64)
+    step = (1 / 20 - 1 / 400) / 63
+    for j in (0, 1, 17, 62, 63):
+        assert abs(orc.list_index(uni, 1.0 / uni[j]) - j) < 1e-9
+    rng = np.random.default_rng(9)
+    for iv in rng.uniform(1 / 600, 1 / 15, 50):
+        assert abs(orc.list_index(uni, iv) - (1 / 20 - iv) / step) < 1e-7
+    geo = 15.0 * 1.07 ** np.arange(40) + np.cumsum(rng.random(40))
+    ivs = rng.uniform(0.5 / geo[-1], 1.5 / geo[0], 200)
+    got = np.array([orc.list_index(geo, iv) for iv in ivs])
+    assert np.allclose(got, _index_interp(geo, ivs), atol=1e-9)
+
+
+def test_level_list_pins(orc):
+    """Finer-level lists: a list uniform in inverse distance stays uniform
+    with the new count; whole fractional indices keep the coarse distances;
+    other points lie on the piecewise-linear inverse-distance profile."""
+    uni = orc.plane_list(20.0, 400.0, 32)
+    for G in (64, 128, 32, 16):
+        got = orc.level_list(uni, G)
+        exp = orc.plane_list(20.0, 400.0, G)
+        assert np.allclose(1 / got, 1 / exp, rtol=0, atol=1e-15), G
+    rng = np.random.default_rng(5)
+    geo = 12.0 * 1.1 ** np.arange(33) + np.cumsum(rng.random(33))
+    fine = orc.level_list(geo, 129)      # 4x: every fourth plane is a coarse one
+    assert np.array_equal(fine[::4], geo)
+    u = np.arange(129) * 32 / 128
+    exp = 1 / np.interp(u, np.arange(33), 1 / geo)
+    assert np.allclose(fine, exp, rtol=1e-13)
+    assert np.all(np.diff(fine) > 0)
+
+
+def test_delta_i_on_an_analytic_plane_with_varying_plane_spacing(orc):
+    """The same slanted plane with a list of varying spacing: the index jump
+    toward each predecessor is the difference of the continuous indices
+    (numpy's interpolation over the list) of the two points' inverse
+    distances, rounded half away from zero and clamped to +-7."""
+    K = np.array([[300.0, 0, 40], [0, 300.0, 30], [0, 0, 1]])
+    Ki, _ = orc.kinv_level(K, 0)
+    n = np.array([0.0, 0.6, -0.8])
+    c = 40.0
+    d, _ = _plane_depth(Ki, n, c, 80, 60)
+    geo = 30.0 * 1.0015 ** np.arange(512)
+    nb = np.broadcast_to(n, (60, 80, 3)).astype(np.float32).copy()
+    dI = orc.delta_i(d.astype(np.float32), nb, Ki, np.array([[0, 0, -1.0]]), [geo])
+    DIRS = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1)]
+    yy, xx = np.mgrid[0:60, 0:80]
+    d32 = d.astype(np.float32).astype(np.float64)
+    ip = 1.0 / d32
+    nonzero = 0
+    for r, (dx, dy) in enumerate(DIRS):
+        # the predecessor's point on the seed's tangent plane (the plane itself)
+        uq, vq = xx - dx + 0.5, yy - dy + 0.5
+        ray_q = np.stack([uq, vq, np.ones_like(uq)], -1) @ Ki.T
+        up, vp = xx + 0.5, yy + 0.5
+        ray_p = np.stack([up, vp, np.ones_like(up)], -1) @ Ki.T
+        dT = (n @ np.moveaxis(d32[..., None] * ray_p, -1, 0).reshape(3, -1)).reshape(60, 80) / (ray_q @ n)
+        iq = 1.0 / dT
+        v = _index_interp(geo, iq.ravel()).reshape(60, 80) - _index_interp(geo, ip.ravel()).reshape(60, 80)
+        v = np.clip(v, -7, 7)
+        exp = np.sign(v) * np.floor(np.abs(v) + 0.5)
+        # rounding decisions within 1e-9 of a half are left out
+        clear = np.abs(np.abs(v) - np.floor(np.abs(v)) - 0.5) > 1e-9
+        got = dI[r, :, :, 0]
+        assert np.array_equal(got[clear], exp[clear]), r
+        nonzero += np.count_nonzero(exp)
+    assert nonzero > 1000

@@ -299,3 +299,43 @@ def test_pg_constant_winner_equals_plain(orc):
     a, _ = orc.sgm(S, [12], 8, lut, ref, 8)
     b, _ = orc.sgm(S, [12], 8, lut, ref, 8, pg=geom)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("fam_n", [(0.0, 0.0, -1.0), (0.0, 0.6, -0.8)])
+def test_pg_locks_onto_an_analytic_slanted_plane(orc, fam_n):
+    """A row of pixels seeing a plane whose plane index in the family's list
+    rises by exactly 2 per pixel (inverse distance affine in x; for the
+    slanted family n_x = 0 keeps n^T K^-1 p constant along the row), with
+    the matching cost 0 on that index and 60 elsewhere: from the third
+    pixel on, the path-gradient offset predicts the jump exactly
+    (extrapolated inverse depth, di = -2), so the path cost at the plane's
+    label is 0, where plain SGM pays P2 every step."""
+    n_px, D, j0, p1, p2 = 14, 40, 3, 5, 30
+    K = np.array([[200.0, 0.0, 7.0], [0.0, 200.0, 0.5], [0.0, 0.0, 1.0]])
+    Ki, _ = orc.kinv_level(K, 0)
+    nf = np.asarray(fam_n, np.float64)
+    deltas = orc.plane_list(20.0, 400.0, D)
+    iv = 1.0 / deltas
+    step = (iv[0] - iv[-1]) / (D - 1)
+    # rays of the row y = 0 and the family's n^T K^-1 p (constant along it)
+    xs = np.arange(n_px) + 0.5
+    rays = np.stack([xs, np.full(n_px, 0.5), np.ones(n_px)], -1) @ Ki.T
+    cf = -(rays @ nf)
+    assert np.allclose(cf, cf[0])
+    S = np.full((1, n_px, D), 60, np.uint8)
+    lab = j0 + 2 * np.arange(n_px)
+    S[0, np.arange(n_px), lab] = 0
+    lut = np.full(256, p2, np.int32)
+    ref = np.zeros((1, n_px), np.uint8)
+    geom = dict(G=[D], fam_delta=deltas, fam_n=nf[None], Kinv=Ki, step=np.array([step]))
+    _, L_pg = orc.sgm(S, [D], p1, lut, ref, 4, want_sbar=False, want_lr=True, pg=geom)
+    _, L_pi = orc.sgm(S, [D], p1, lut, ref, 4, want_sbar=False, want_lr=True)
+    at_pg = L_pg[0, 0, np.arange(n_px), lab].astype(int)
+    at_pi = L_pi[0, 0, np.arange(n_px), lab].astype(int)
+    assert at_pg[0] == 0 and at_pg[1] == p2
+    assert np.all(at_pg[2:] == 0), at_pg
+    assert np.all(at_pi[1:] == p2), at_pi
+    # the planes of the winning labels lie on one scene plane: their points'
+    # inverse depth is affine along the row (what the extrapolation uses)
+    inv_depth = cf / deltas[lab]
+    assert np.allclose(np.diff(inv_depth, 2), 0, atol=1e-15)
