@@ -249,6 +249,19 @@ fassmvs_status fassmvs_cross_ratio_planes(const double K[9], int32_t w, int32_t 
 fassmvs_status fassmvs_filter_dog(fassmvs_handle *h, const uint8_t *img, int32_t w, int32_t hgt, float *depth,
                                   float *normal, float *confidence, uint8_t *mask_out);
 
+/* Allocation-free DoG texture filter, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same filter and results as
+ * fassmvs_filter_dog, with its scratch (a double image and two u8 masks,
+ * 10 bytes per pixel) in a static device array of 40 MiB that each device
+ * holds from module load until the process ends.  Calls no allocating
+ * routine.  Images of more than 4194304 pixels (2^22) are rejected with
+ * EINVAL.  Every call on one device shares that device's array, so calls
+ * that overlap on one device (several handles or threads) race; serialise
+ * them.  Synchronous on the handle's stream like fassmvs_filter_dog. */
+fassmvs_status fassmvs_filter_dog_noalloc(fassmvs_handle *h, const uint8_t *img, int32_t w, int32_t hgt,
+                                          float *depth, float *normal, float *confidence, uint8_t *mask_out);
+
 /* Geometric consistency by mutual reprojection (Alg. 4) of a reference depth
  * map against n_nb (1..8) neighbouring depth maps of the same size:
  * depth_nb[k] device pointers, R_rel / t_rel host arrays (n_nb x 9, n_nb x 3,

@@ -97,6 +97,7 @@ def _declare(L):
         "fassmvs_stage_cost": (st, [vp, i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "fassmvs_stage_cost_ncc": (st, [vp, i32, i32, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         "fassmvs_filter_dog": (st, [vp, vp, i32, i32, vp, vp, vp, vp]),
+        "fassmvs_filter_dog_noalloc": (st, [vp, vp, i32, i32, vp, vp, vp, vp]),
         "fassmvs_bounding_planes": (st, [vp, i32, i32, vp, dbl, dbl, vp]),
         "fassmvs_frame_footprint": (st, [vp, i32, i32, i32, vp, i32, vp]),
         "fassmvs_server_create": (st, [vp, i32, u64, vp]),
@@ -515,6 +516,15 @@ class Handle:
         h, w = img.shape
         mask = self.empty((h, w), np.uint8) if want_mask else None
         self._check(lib().fassmvs_filter_dog(self.h, img.vp, w, h, _vp(depth), _vp(normal), _vp(conf), _vp(mask)))
+        return mask
+
+    def filter_dog_noalloc(self, img: DeviceArray, depth=None, normal=None, conf=None, mask=None):
+        """The allocation-free DoG filter (its scratch in the library's static
+        device array): maps modified in place, the mask written into the
+        caller's device array ``mask`` when given."""
+        h, w = img.shape
+        self._check(lib().fassmvs_filter_dog_noalloc(self.h, img.vp, w, h, _vp(depth), _vp(normal), _vp(conf),
+                                                     _vp(mask)))
         return mask
 
     def filter_geometric(self, K, depth: DeviceArray, nb_depths, R_rel, t_rel, eta_r=10.0, eta_h=3, normal=None,

@@ -34,6 +34,35 @@ const char *kStageNames[ST_COUNT] = {"upload", "pyramid", "census", "sweep", "sg
 
 std::string g_create_error;
 
+// Scratch of the allocation-free DoG filter (fassmvs_filter_dog_noalloc): the
+// horizontal Gaussian pass (double) and the two mask images (u8) of at most
+// kNoAllocMaxPixels pixels.  Each device holds its own copy from module load
+// until the process ends; its address is looked up once per device, with
+// that device current, when the first handle on it is created.
+constexpr size_t kNoAllocMaxPixels = (size_t)1 << 22;
+constexpr size_t kNoAllocBytes = kNoAllocMaxPixels * 10;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the device must be
+// current).  Returns nullptr if the lookup fails.
+void *scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
+
 __global__ void k_fill(uint8_t *p, uint8_t v, size_t n) {
     size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = v;
@@ -1094,6 +1123,10 @@ fassmvs_status fassmvs_create(const fassmvs_config *cfg, fassmvs_handle **out) {
         g_create_error = "hipSetDevice failed";
         return FASSMVS_EDEVICE;
     }
+    if (!scratch_address(cfg->device)) {
+        g_create_error = "scratch symbol lookup failed";
+        return FASSMVS_EDEVICE;
+    }
     fassmvs_handle *h = new fassmvs_handle();
     h->cfg = *cfg;
     if (cfg->stream) {
@@ -1608,6 +1641,26 @@ fassmvs_status fassmvs_filter_dog(fassmvs_handle *h, const uint8_t *img, int32_t
     HIPCHK(h, launch_apply_keep((const uint8_t *)h->post_m1.p, N, depth, normal, confidence, h->stream), "dog apply");
     if (mask_out)
         HIPCHK(h, hipMemcpyAsync(mask_out, h->post_m1.p, N, hipMemcpyDeviceToDevice, h->stream), "mask copy");
+    STAGE_END;
+}
+
+fassmvs_status fassmvs_filter_dog_noalloc(fassmvs_handle *h, const uint8_t *img, int32_t w, int32_t hgt,
+                                          float *depth, float *normal, float *confidence, uint8_t *mask_out) {
+    STAGE_BEGIN;
+    if (!img || w < 1 || hgt < 1) return fail(h, FASSMVS_EINVAL, "bad DoG arguments");
+    const size_t N = (size_t)w * hgt;
+    if (N > kNoAllocMaxPixels)
+        return fail(h, FASSMVS_EINVAL, "image exceeds the allocation-free filter's maximum of 4194304 pixels");
+    // the address looked up when the handle was created on this device;
+    // never the array's host-side name
+    uint8_t *base = (uint8_t *)scratch_address(h->cfg.device);
+    if (!base) return fail(h, FASSMVS_EDEVICE, "scratch address missing");
+    double *tmp = (double *)base;
+    uint8_t *m0 = base + N * 8, *m1 = m0 + N;
+    PostArgs pa = dog_args();
+    HIPCHK(h, launch_dog_mask(img, w, hgt, pa, tmp, m0, m1, h->stream), "dog filter");
+    HIPCHK(h, launch_apply_keep(m1, N, depth, normal, confidence, h->stream), "dog apply");
+    if (mask_out) HIPCHK(h, hipMemcpyAsync(mask_out, m1, N, hipMemcpyDeviceToDevice, h->stream), "mask copy");
     STAGE_END;
 }
 
