@@ -342,11 +342,42 @@ def batch_bench(fm, frames, repeats):
             for i, t in enumerate(tickets):
                 wait(i, t)
             best_all = min(best_all, time.perf_counter() - t0)
+        # one batch on one handle: per level round one sweep launch and one
+        # persistent aggregation launch for all frames, replayed as a graph
+        bh = fm.Handle(fm.config_from_params(frames[0]["params"]))
+        try:
+            wls = [dict(wl, ref=inputs[i][0], views=inputs[i][1]) for i, wl in enumerate(frames)]
+
+            def run_batch():
+                t = bh.submit_batch(wls, mem_kind=fm.MEM_DEVICE)
+                for i in range(len(frames)):
+                    d, n, c = inputs[i][2]
+                    bh.poll_batch(t, i, d, n, c, mem_kind=fm.MEM_DEVICE)
+
+            run_batch()   # tuning, capture
+            tuning = bh.batch_tuning()
+            best_batch = float("inf")
+            for _ in range(repeats):
+                t0 = time.perf_counter()
+                run_batch()
+                best_batch = min(best_batch, time.perf_counter() - t0)
+            os.environ["FASSMVS_BATCH_GRAPH"] = "0"
+            best_eager = float("inf")
+            try:
+                for _ in range(repeats):
+                    t0 = time.perf_counter()
+                    run_batch()
+                    best_eager = min(best_eager, time.perf_counter() - t0)
+            finally:
+                del os.environ["FASSMVS_BATCH_GRAPH"]
+        finally:
+            bh.close()
     finally:
         for h in handles:
             h.close()
-    res = {"frames": len(frames), "pixel_hyp": hyp}
-    for name, t in (("one_at_a_time", best_seq), ("all_in_flight", best_all)):
+    res = {"frames": len(frames), "pixel_hyp": hyp, "batch_tuning": tuning}
+    for name, t in (("one_at_a_time", best_seq), ("all_in_flight", best_all), ("one_batch_graph", best_batch),
+                    ("one_batch_eager", best_eager)):
         res[name] = {"ms": round(t * 1e3, 2), "frames_per_s": round(len(frames) / t, 1),
                      "mpx_hyp_per_s": round(hyp / 1e6 / t, 1)}
     return res

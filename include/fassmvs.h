@@ -171,6 +171,48 @@ fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref,
 fassmvs_status fassmvs_poll(fassmvs_handle *h, uint64_t ticket, float *depth, float *normal, float *confidence,
                             int32_t mem_kind, int32_t wait_ms);
 
+/* ---------------------------------------------------------------------
+ * Batched frames: several bundles of uneven size, views, plane count and
+ * pyramid height in one submission.  The frames run level round by level
+ * round (every frame's coarsest level first); in each round the sweeps of
+ * all frames are one launch and their aggregations one persistent launch
+ * over the paths of every frame and direction; the whole batch is captured
+ * in a HIP graph once per batch shape and replayed while the shape and the
+ * buffers stay; the sweep's tile height and workgroup count are tuned once
+ * per shape by timing the candidates (they change no result).  Each frame's
+ * maps are those fassmvs_submit_frame gives for the same bundle.
+ * --------------------------------------------------------------------- */
+#define FASSMVS_MAX_BATCH 64
+
+typedef struct {
+    const fassmvs_image *ref;        /* as fassmvs_submit_frame */
+    const fassmvs_image *views;
+    const int8_t *view_side;
+    int32_t n_views;
+    const double *K;                 /* 9 values, row-major */
+    const fassmvs_plane_family *families;
+    int32_t n_families;
+    int32_t n_levels;                /* pyramid height of this frame; 0: the handle's */
+    int32_t window_labels;           /* labels per family below the coarsest level; -1: the handle's */
+} fassmvs_frame;
+
+/* Enqueue n_frames (1..64) frames as one batch on the handle's stream.
+ * Pixels as in fassmvs_submit_frame (host memory copied before return, or
+ * device memory read on the stream).  The handle holds no other frame while
+ * the batch runs (EBUSY).  Errors as fassmvs_submit_frame, naming the frame. */
+fassmvs_status fassmvs_submit_batch(fassmvs_handle *h, const fassmvs_frame *frames, int32_t n_frames, int32_t mem_kind,
+                                    uint64_t *ticket);
+
+/* Maps of frame `index` of a batch (as fassmvs_poll); PENDING while the batch
+ * runs.  The maps stay available until the next submission. */
+fassmvs_status fassmvs_poll_batch(fassmvs_handle *h, uint64_t ticket, int32_t index, float *depth, float *normal,
+                                  float *confidence, int32_t mem_kind, int32_t wait_ms);
+
+/* The sweep configuration the batch tuner chose for the last batch shape:
+ * rows per thread (tile height / 4), workgroup target, and the measured
+ * sweep time of the batch in ms. */
+fassmvs_status fassmvs_batch_tuning(fassmvs_handle *h, int32_t *rows_per_thread, int32_t *sweep_blocks, double *ms);
+
 /* Wait for any frame in flight and release every resource of the handle. */
 void fassmvs_destroy(fassmvs_handle *h);
 

@@ -79,6 +79,9 @@ def _declare(L):
         "fassmvs_create": (st, [vp, vp]),
         "fassmvs_submit_frame": (st, [vp, vp, vp, vp, i32, vp, vp, i32, i32, vp]),
         "fassmvs_poll": (st, [vp, u64, vp, vp, vp, i32, i32]),
+        "fassmvs_submit_batch": (st, [vp, vp, i32, i32, vp]),
+        "fassmvs_poll_batch": (st, [vp, u64, i32, vp, vp, vp, i32, i32]),
+        "fassmvs_batch_tuning": (st, [vp, vp, vp, vp]),
         "fassmvs_destroy": (None, [vp]),
         "fassmvs_last_error": (C.c_char_p, [vp]),
         "fassmvs_stage_times": (st, [vp, vp, vp, i32]),
@@ -210,6 +213,12 @@ def _families(families):
             fams[i].count = int(f["count"])
     fams._lists = keep
     return fams
+
+
+class Frame(C.Structure):
+    _fields_ = [("ref", C.c_void_p), ("views", C.c_void_p), ("view_side", C.c_void_p), ("n_views", C.c_int32),
+                ("K", C.c_void_p), ("families", C.c_void_p), ("n_families", C.c_int32), ("n_levels", C.c_int32),
+                ("window_labels", C.c_int32)]
 
 
 class Server:
@@ -380,13 +389,8 @@ class Handle:
         self._check(lib().fassmvs_synchronize(self.h))
 
     # ---------------------------------------------------------------- frames
-    def submit_frame(self, ref, views, side, K, families, mem_kind=MEM_HOST):
-        """ref / views: dicts with 'img' (numpy uint8 HxW, or DeviceArray with
-        mem_kind=MEM_DEVICE), 'R' (3x3), 't' (3).  families: dicts with 'n' and
-        'delta_min', 'delta_max', 'count', or an explicit list 'delta', or a
-        depth range 'depth_min', 'depth_max' (see _families)."""
-        keep = []
-
+    @staticmethod
+    def _frame_args(ref, views, side, K, families, keep):
         def mk(v):
             im = Image()
             img = v["img"]
@@ -408,10 +412,59 @@ class Handle:
         sd = (C.c_int8 * len(side))(*side)
         Kc = (C.c_double * 9)(*[float(x) for x in np.asarray(K, np.float64).ravel()])
         fams = _families(families)
+        keep += [r, vs, sd, Kc, fams]
+        return r, vs, sd, Kc, fams
+
+    def submit_frame(self, ref, views, side, K, families, mem_kind=MEM_HOST):
+        """ref / views: dicts with 'img' (numpy uint8 HxW, or DeviceArray with
+        mem_kind=MEM_DEVICE), 'R' (3x3), 't' (3).  families: dicts with 'n' and
+        'delta_min', 'delta_max', 'count', or an explicit list 'delta', or a
+        depth range 'depth_min', 'depth_max' (see _families)."""
+        keep = []
+        r, vs, sd, Kc, fams = self._frame_args(ref, views, side, K, families, keep)
         t = C.c_uint64()
         self._check(lib().fassmvs_submit_frame(self.h, C.byref(r), vs, sd, len(views), Kc, fams, len(families),
                                                mem_kind, C.byref(t)))
         return t.value
+
+    def submit_batch(self, workloads, mem_kind=MEM_HOST):
+        """Several scenegen-style frames (dicts with ref, views, side, K,
+        families and optionally params n_levels / window_labels) as one batch."""
+        keep = []
+        frames = (Frame * len(workloads))()
+        for i, wl in enumerate(workloads):
+            r, vs, sd, Kc, fams = self._frame_args(wl["ref"], wl["views"], wl["side"], wl["K"], wl["families"], keep)
+            f = frames[i]
+            f.ref, f.views, f.view_side, f.K, f.families = (C.addressof(r), C.addressof(vs), C.addressof(sd),
+                                                             C.addressof(Kc), C.addressof(fams))
+            f.n_views, f.n_families = len(wl["views"]), len(wl["families"])
+            prm = wl.get("params", {})
+            f.n_levels = int(prm.get("n_levels", 0))
+            f.window_labels = int(prm.get("window_labels", -1))
+        t = C.c_uint64()
+        self._check(lib().fassmvs_submit_batch(self.h, frames, len(workloads), mem_kind, C.byref(t)))
+        return t.value
+
+    def poll_batch(self, ticket, index, depth=None, normal=None, conf=None, mem_kind=MEM_HOST, wait_ms=-1):
+        return self._check(lib().fassmvs_poll_batch(self.h, ticket, index, _ptr(depth), _ptr(normal), _ptr(conf),
+                                                    mem_kind, wait_ms))
+
+    def run_batch(self, workloads):
+        """Run frames as one batch; returns host depth/normal/conf per frame."""
+        t = self.submit_batch(workloads)
+        out = []
+        for i, wl in enumerate(workloads):
+            h, w = wl["height"], wl["width"]
+            m = dict(depth=np.zeros((h, w), np.float32), normal=np.zeros((h, w, 3), np.float32),
+                     conf=np.zeros((h, w), np.float32))
+            self.poll_batch(t, i, m["depth"], m["normal"], m["conf"])
+            out.append(m)
+        return out
+
+    def batch_tuning(self):
+        rpt, blocks, ms = C.c_int32(), C.c_int32(), C.c_double()
+        self._check(lib().fassmvs_batch_tuning(self.h, C.byref(rpt), C.byref(blocks), C.byref(ms)))
+        return dict(rows_per_thread=rpt.value, sweep_blocks=blocks.value, sweep_ms=ms.value)
 
     def poll(self, ticket, depth=None, normal=None, conf=None, mem_kind=MEM_HOST, wait_ms=-1):
         st = self._check(lib().fassmvs_poll(self.h, ticket, _ptr(depth), _ptr(normal), _ptr(conf),

@@ -51,6 +51,49 @@ __device__ __forceinline__ float warp_sample(const uint8_t *__restrict__ src, in
     return __builtin_fmaf(ay, bot - top, top);
 }
 
+// warp_sample for a reference region whose samples all map in front of the
+// view and inside [0, sw - 2] x [0, sh - 2] (warp_region_mode): there the
+// reciprocal guard and the border clamps change nothing, so the same
+// operations without them give the same value.  The texel offset is clamped
+// to the image only as a memory guard.
+__device__ __forceinline__ float warp_sample_inside(const uint8_t *__restrict__ src, int sw, int sh, double h0,
+                                                    double h1, double h2, double h3, double h4, double h5, double h6,
+                                                    double h7, double h8, double qx, double qy) {
+    const double hx = __builtin_fma(h0, qx, __builtin_fma(h1, qy, h2));
+    const double hy = __builtin_fma(h3, qx, __builtin_fma(h4, qy, h5));
+    const double hz = __builtin_fma(h6, qx, __builtin_fma(h7, qy, h8));
+    const double r = 1.0 / hz;
+    const double sx = __builtin_fma(hx, r, -0.5);
+    const double sy = __builtin_fma(hy, r, -0.5);
+    const uint32_t xa = (uint32_t)(int)sx, ya = (uint32_t)(int)sy;
+    const float ax = (float)__builtin_amdgcn_fract(sx);
+    const float ay = (float)__builtin_amdgcn_fract(sy);
+    const uint32_t b0 = min(__umul24(ya, (uint32_t)sw) + xa, (uint32_t)(sw * (sh - 1) - 2));
+    const uint32_t b1 = b0 + (uint32_t)sw;
+    const float i00 = (float)src[b0];
+    const float i10 = (float)src[b0 + 1u];
+    const float i01 = (float)src[b1];
+    const float i11 = (float)src[b1 + 1u];
+    const float top = __builtin_fmaf(ax, i10 - i00, i00);
+    const float bot = __builtin_fmaf(ax, i11 - i01, i01);
+    return __builtin_fmaf(ay, bot - top, top);
+}
+
+// Whether every sample of the region with corner sample points (qx_lo..qx_hi)
+// x (qy_lo..qy_hi) maps in front of the view and inside [0, sw - 2] x
+// [0, sh - 2] (with a 1e-6 px margin for rounding): hz is affine, so a
+// region in front of the view maps to the convex quadrilateral of its
+// corners' images.  corner selects the corner (bit 0: x, bit 1: y).
+__device__ __forceinline__ bool warp_corner_inside(const double *H, int corner, double qx_lo, double qx_hi,
+                                                   double qy_lo, double qy_hi, int sw, int sh) {
+    const double qx = (corner & 1) ? qx_hi : qx_lo, qy = (corner & 2) ? qy_hi : qy_lo;
+    const double hz = H[6] * qx + H[7] * qy + H[8];
+    if (!(hz > 1e-200)) return false;
+    const double X = (H[0] * qx + H[1] * qy + H[2]) / hz - 0.5;
+    const double Y = (H[3] * qx + H[4] * qy + H[5]) / hz - 0.5;
+    return X >= 1e-6 && X <= (double)(sw - 2) - 1e-6 && Y >= 1e-6 && Y <= (double)(sh - 2) - 1e-6;
+}
+
 // Minimum over the 64 lanes of a wavefront: DPP within each row of 16
 // (quad_perm, row_half_mirror, row_mirror), then row_bcast:15 and
 // row_bcast:31 carry the row minima up to lane 63, which is read back.

@@ -292,21 +292,19 @@ hipError_t launch_normals(const NormalArgs &a, hipStream_t s) {
 
 // --------------------------------------------------------------- seeds
 // Continuous index of the inverse distance iv in a plane list of G >= 2
-// increasing distances: bisection for the last interval start i in
-// [0, G-2] whose plane's inverse distance is >= iv (0 if none), then the
-// linear position inside that interval (end intervals extended beyond the
-// list).
-__device__ double list_index(const double *__restrict__ d, int G, double iv) {
-    int lo = 0, hi = G - 2;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (1.0 / d[mid] >= iv)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const double a = 1.0 / d[lo], b = 1.0 / d[lo + 1];
-    return (double)lo + (a - iv) / (a - b);
+// planes given by their inverse distances inv[0..G-1] (decreasing): the
+// interval start i is the last one in [0, G-2] whose plane's inverse
+// distance is >= iv (0 if none) -- from a guess by the list's mean spacing
+// (rspan = (G - 1) / (inv[0] - inv[G-1])) and the few steps to it -- then
+// the linear position inside that interval (end intervals extended beyond
+// the list).
+__device__ double list_index(const double *__restrict__ inv, int G, double rspan, double iv) {
+    const double gd = fmin(fmax((inv[0] - iv) * rspan, 0.0), (double)(G - 2));
+    int i = (int)gd;
+    while (i < G - 2 && inv[i + 1] >= iv) ++i;
+    while (i > 0 && inv[i] < iv) --i;
+    const double a = inv[i], b = inv[i + 1];
+    return (double)i + (a - iv) / (a - b);
 }
 
 // Coarse-to-fine initialisation: nearest-neighbour upsampling of depth and
@@ -332,15 +330,19 @@ __global__ __launch_bounds__(256) void k_seed(const SeedArgs a) {
     double rp[3];
     ray_of(a.Kinv, x + 0.5, y + 0.5, rp);
     double d = dbf;
+    double rspan[kMaxFam], jp[kMaxFam];
     for (int f = 0; f < a.n_fam; ++f) {
+        const double *inv = a.inv + a.goff[f];
+        rspan[f] = (double)(a.G[f] - 1) / (inv[0] - inv[a.G[f] - 1]);
         const double *n = a.fam_n[f];
         double c = -(n[0] * rp[0] + n[1] * rp[1] + n[2] * rp[2]);
         int o;
+        jp[f] = 0.0;
         if (!(d > 0.0) || !(c > 0.0)) {
             o = (a.G[f] - a.W[f]) / 2;
         } else {
             double delta = d * c;
-            double j = list_index(a.delta + a.goff[f], a.G[f], 1.0 / delta);
+            double j = list_index(inv, a.G[f], rspan[f], 1.0 / delta);
             j = fmin(fmax(j, -1.0e6), 1.0e6);
             int jr = (int)floor(j + 0.5);
             o = clampi(jr - a.W[f] / 2, 0, a.G[f] - a.W[f]);
@@ -353,6 +355,12 @@ __global__ __launch_bounds__(256) void k_seed(const SeedArgs a) {
     double nb[3] = {nb0, nb1, nb2};
     if (!(d > 0.0) || (nb[0] == 0.0 && nb[1] == 0.0 && nb[2] == 0.0)) return;
     double kP = nb[0] * (d * rp[0]) + nb[1] * (d * rp[1]) + nb[2] * (d * rp[2]);
+    // the seed point's continuous index per family (the same for every path)
+    for (int f = 0; f < a.n_fam; ++f) {
+        const double *n = a.fam_n[f];
+        const double cp = -(n[0] * rp[0] + n[1] * rp[1] + n[2] * rp[2]);
+        if (cp > 0.0) jp[f] = list_index(a.inv + a.goff[f], a.G[f], rspan[f], 1.0 / (d * cp));
+    }
     for (int r = 0; r < 8; ++r) {
         double rq[3];
         ray_of(a.Kinv, (x - dir_dx(r)) + 0.5, (y - dir_dy(r)) + 0.5, rq);
@@ -365,10 +373,8 @@ __global__ __launch_bounds__(256) void k_seed(const SeedArgs a) {
             double cp = -(n[0] * rp[0] + n[1] * rp[1] + n[2] * rp[2]);
             double cq = -(n[0] * rq[0] + n[1] * rq[1] + n[2] * rq[2]);
             if (!(cp > 0.0) || !(cq > 0.0)) continue;
-            double ip = 1.0 / (d * cp);
             double iq = 1.0 / (dT * cq);
-            const double *list = a.delta + a.goff[f];
-            double v = list_index(list, a.G[f], iq) - list_index(list, a.G[f], ip);
+            double v = list_index(a.inv + a.goff[f], a.G[f], rspan[f], iq) - jp[f];
             v = fmin(fmax(v, -7.0), 7.0);
             a.dI[((size_t)r * N + p) * a.n_fam + f] = (int8_t)round(v);
         }

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 
 namespace fmvs {
 
@@ -14,6 +15,14 @@ extern template void sgm_launch_pk<1>(const SgmArgs &, bool, bool, dim3, hipStre
 extern template void sgm_launch_pk<2>(const SgmArgs &, bool, bool, dim3, hipStream_t);
 extern template void sgm_launch_pk<3>(const SgmArgs &, bool, bool, dim3, hipStream_t);
 extern template void sgm_launch_pk<4>(const SgmArgs &, bool, bool, dim3, hipStream_t);
+extern template hipError_t sgm_launch_pk_jobs<1>(const SgmArgs *, const int *, int, unsigned *, bool, bool, int, int,
+                                                 hipStream_t);
+extern template hipError_t sgm_launch_pk_jobs<2>(const SgmArgs *, const int *, int, unsigned *, bool, bool, int, int,
+                                                 hipStream_t);
+extern template hipError_t sgm_launch_pk_jobs<3>(const SgmArgs *, const int *, int, unsigned *, bool, bool, int, int,
+                                                 hipStream_t);
+extern template hipError_t sgm_launch_pk_jobs<4>(const SgmArgs *, const int *, int, unsigned *, bool, bool, int, int,
+                                                 hipStream_t);
 
 int sgm_paths(int dir, int w, int h) {
     int dx = dir_dx(dir), dy = dir_dy(dir);
@@ -214,6 +223,10 @@ static void launch_k(const SgmArgs &a, bool win, bool sn, dim3 grid, hipStream_t
 
 // Packed two-label kernel when every family window is even (all variants);
 // the one-label kernel otherwise.
+__global__ void k_zero_u32(unsigned *p) {
+    if (threadIdx.x == 0) *p = 0u;
+}
+
 static bool use_packed(const SgmArgs &a) {
     if (a.final_mode || (a.D & 1)) return false;
     for (int f = 0; f < a.n_fam; ++f)
@@ -257,6 +270,64 @@ hipError_t launch_sgm(const SgmArgs &a0, hipStream_t s) {
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Several frames' aggregation in one persistent launch (two steps, as for
+// the sweep).  prepare_sgm_batch: host[0..n-1] are the frames' args, each
+// with its directions and output buffers set (write mode, no path gradient,
+// even label counts and windows so the two-label kernel applies, at most 4
+// families, the same windows / surface-normal choice); their path prefix
+// per direction is set and they are written with the job prefix (n + 1
+// ints) to out (host memory of sgm_batch_bytes(n)).  Returns the job count
+// (paths over all frames), or -1 if the frames cannot share a launch; *kp,
+// *win, *sn, *nf_max receive the kernel variant.
+size_t sgm_batch_bytes(int n) { return sizeof(SgmArgs) * n + sizeof(int) * (n + 1); }
+
+int prepare_sgm_batch(SgmArgs *host, int n, void *out, int *kp, bool *win, bool *sn, int *nf_max) {
+    if (n < 1) return -1;
+    int *prefix = (int *)((SgmArgs *)out + n);
+    prefix[0] = 0;
+    *kp = 1;
+    *nf_max = 1;
+    *win = host[0].offs != nullptr;
+    *sn = host[0].dI != nullptr;
+    for (int i = 0; i < n; ++i) {
+        SgmArgs &a = host[i];
+        if (a.pg || a.final_mode || !use_packed(a) || a.n_fam > 4 || (a.offs != nullptr) != *win ||
+            (a.dI != nullptr) != *sn)
+            return -1;
+        a.path_begin[0] = 0;
+        for (int d = 0; d < a.n_dirs; ++d) a.path_begin[d + 1] = a.path_begin[d] + sgm_paths(a.dirs[d], a.w, a.h);
+        for (int d = a.n_dirs + 1; d < 9; ++d) a.path_begin[d] = a.path_begin[a.n_dirs];
+        prefix[i + 1] = prefix[i] + a.path_begin[a.n_dirs];
+        *kp = std::max(*kp, (a.D + 127) / 128);
+        *nf_max = std::max(*nf_max, a.n_fam);
+    }
+    if (*kp > 4) return -1;
+    std::memcpy(out, host, sizeof(SgmArgs) * n);
+    return prefix[n];
+}
+
+// launch_sgm_batch: the args block prepared above in device memory at dev;
+// counter: a device word the launch takes jobs from, cleared here by a fill
+// kernel.  The grid holds up to six workgroups per CU; every wavefront
+// leaves when the jobs run out.
+hipError_t launch_sgm_batch(const void *dev, int n, int jobs, int kp, bool win, bool sn, int nf_max,
+                            unsigned *counter, hipStream_t s) {
+    if (jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const SgmArgs *dl = (const SgmArgs *)dev;
+    const int *dp = (const int *)((const SgmArgs *)dev + n);
+    const int blocks = std::min((jobs + WAVES - 1) / WAVES, 256 * 6);
+    switch (kp) {
+        case 1: return sgm_launch_pk_jobs<1>(dl, dp, n, counter, win, sn, nf_max, blocks, s);
+        case 2: return sgm_launch_pk_jobs<2>(dl, dp, n, counter, win, sn, nf_max, blocks, s);
+        case 3: return sgm_launch_pk_jobs<3>(dl, dp, n, counter, win, sn, nf_max, blocks, s);
+        case 4: return sgm_launch_pk_jobs<4>(dl, dp, n, counter, win, sn, nf_max, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace fmvs

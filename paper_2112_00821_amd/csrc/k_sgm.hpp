@@ -305,35 +305,50 @@ __device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(
 // operand, and lanes past the label count read 0 and drop their stores by
 // the resource's range check.  With PG the same kernel runs the
 // path-gradient variant (Eq. sgm-smooth-pg).
+// Wave-uniform copies of values read from an argument block (its arrays
+// indexed by a uniform index stay uniform, wherever the block lives).
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ T *rflp(T *p) {
+    const uint64_t u = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *p, int bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
 }
 
+constexpr int PK_G2 = 6;
+constexpr int PK_LW = (kMaxLabels + 2 * PK_G2 * kMaxFam) / 2 + 1;   // 32-bit words per buffer, last one a sink
+
+// One path of the two-label kernel: path index `path` of the frame a (all
+// its directions' paths numbered by a.path_begin), run by one wavefront with
+// the P2 table s_lut and (path gradient) the plane lists pdelta in LDS, and
+// buf0 / buf1 its two LDS predecessor buffers.
 template <int KP, int NF, bool WIN, bool SN, bool PG>
-__global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
+__device__ __forceinline__ void sgm_pk_path(const SgmArgs a, const int path, const int *s_lut,
+                                            const double *pdelta, uint32_t *buf0, uint32_t *buf1) {
     constexpr int PF = 16;
-    constexpr int G2 = 6;
-    constexpr int LW = (kMaxLabels + 2 * G2 * kMaxFam) / 2 + 1;   // 32-bit words per buffer, last one a sink
-    __shared__ uint32_t lbuf[WAVES][2][LW];
-    __shared__ int s_lut[256];   // P2 by intensity change
-    __shared__ double pdelta[PG ? kMaxPgPlanes : 1];   // path gradient: the level's plane lists
-    for (int i = threadIdx.x; i < 256; i += 64 * WAVES) s_lut[i] = a.lut[i];
-    if (PG)
-        for (int i = threadIdx.x; i < a.sumG; i += 64 * WAVES) pdelta[i] = a.delta[i];
-    __syncthreads();
+    constexpr int G2 = PK_G2;
+    constexpr int LW = PK_LW;
     const int lane = threadIdx.x & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int path = blockIdx.x * WAVES + wid;
-    if (path >= a.path_begin[a.n_dirs]) return;
+    // the argument block's scalars as wave-uniform locals (the block may sit
+    // in registers, private memory or global memory depending on the caller)
+    const int aw = rfl(a.w), ah = rfl(a.h);
+    const uint8_t *__restrict__ aref = rflp(a.ref);
+    const int32_t *__restrict__ aoffs = rflp(a.offs);
+    const int8_t *__restrict__ adI = rflp(a.dI);
     int slot = 0;
-    while (path >= a.path_begin[slot + 1]) ++slot;
-    const int dir = a.dirs[slot];
-    const PathGeom pg = path_geom(dir, path - a.path_begin[slot], a.w, a.h);
-    const size_t N = (size_t)a.w * a.h;
-    const int D = a.D;
-    const int F = NF == 1 ? 1 : a.n_fam;
-    const long pstride = (long)pg.dy * a.w + pg.dx;
-    const long p0 = (long)pg.sy * a.w + pg.sx;
+    while (path >= rfl(a.path_begin[slot + 1])) ++slot;
+    const int dir = rfl(a.dirs[slot]);
+    const PathGeom pg = path_geom(dir, path - rfl(a.path_begin[slot]), aw, ah);
+    const size_t N = (size_t)aw * ah;
+    const int D = rfl(a.D);
+    const int F = NF == 1 ? 1 : rfl(a.n_fam);
+    const long pstride = (long)pg.dy * aw + pg.dx;
+    const long p0 = (long)pg.sy * aw + pg.sx;
     const int len = pg.len;
     const bool all_valid = D == 128 * KP;
 
@@ -355,16 +370,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
         seg[k] = sb;
         widx[k] = lv[k] ? (sb + li[k]) >> 1 : LW - 1;
     }
-    uint32_t *buf0 = lbuf[wid][0];
-    uint32_t *buf1 = lbuf[wid][1];
     for (int i = lane; i < LW; i += 64) {
         buf0[i] = 0xFFFFFFFFu;
         buf1[i] = 0xFFFFFFFFu;
     }
     __builtin_amdgcn_wave_barrier();
 
-    const uint8_t *__restrict__ S = a.S;
-    uint16_t *__restrict__ out = a.out[slot];
+    const uint8_t *__restrict__ S = rflp(a.S);
+    uint16_t *__restrict__ out = rflp(a.out[slot]);
 
     // Uniform per-step values of one block of PF steps, one vector load per
     // quantity (lane j holds step t0 + j, j < PF): the penalty P2 of the
@@ -384,13 +397,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
         const int t = tl < len ? tl : len - 1;
         const long p = p0 + (long)t * pstride;
         const long pp = p0 + (long)(t > 0 ? t - 1 : 0) * pstride;
-        r.i0 = a.ref[p];
-        r.i1 = a.ref[pp];
+        r.i0 = aref[p];
+        r.i1 = aref[pp];
         r.first = t == 0;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            r.off[f] = (WIN && f < F) ? a.offs[(size_t)f * N + p] : 0;
-            r.di[f] = (SN && f < F) ? (int)a.dI[((size_t)dir * N + p) * F + f] : 0;
+            r.off[f] = (WIN && f < F) ? aoffs[(size_t)f * N + p] : 0;
+            r.di[f] = (SN && f < F) ? (int)adI[((size_t)dir * N + p) * F + f] : 0;
         }
     };
     int c_ref;
@@ -477,7 +490,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
         {
             // splats of uniform 16-bit values (the packed instructions take
             // them as one scalar operand)
-            const uint32_t P1 = (uint32_t)a.p1;
+            const uint32_t P1 = (uint32_t)rfl(a.p1);
             const u16x2 p1v = (u16x2)(uint16_t)P1;
             const u16x2 mqv = (u16x2)(uint16_t)Mq;
             const uint16_t fl = (uint16_t)(Mq + P2);
@@ -624,6 +637,80 @@ __global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
     }
 }
 
+template <int KP, int NF, bool WIN, bool SN, bool PG>
+__global__ __launch_bounds__(64 * WAVES) void k_sgm_pk(const SgmArgs a) {
+    __shared__ uint32_t lbuf[WAVES][2][PK_LW];
+    __shared__ int s_lut[256];   // P2 by intensity change
+    __shared__ double pdelta[PG ? kMaxPgPlanes : 1];   // path gradient: the level's plane lists
+    for (int i = threadIdx.x; i < 256; i += 64 * WAVES) s_lut[i] = a.lut[i];
+    if (PG)
+        for (int i = threadIdx.x; i < a.sumG; i += 64 * WAVES) pdelta[i] = a.delta[i];
+    __syncthreads();
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int path = blockIdx.x * WAVES + wid;
+    if (path >= a.path_begin[a.n_dirs]) return;
+    sgm_pk_path<KP, NF, WIN, SN, PG>(a, path, s_lut, pdelta, lbuf[wid][0], lbuf[wid][1]);
+}
+
+// The fields the aggregation reads of a frame's arguments in device memory,
+// as wave-uniform values (the frame index is uniform, so are its fields).
+__device__ __forceinline__ SgmArgs uniform_sgm_args(const SgmArgs *__restrict__ p) {
+    SgmArgs a;
+    a.w = rfl(p->w);
+    a.h = rfl(p->h);
+    a.D = rfl(p->D);
+    a.n_fam = rfl(p->n_fam);
+    for (int f = 0; f < kMaxFam; ++f) {
+        a.W[f] = rfl(p->W[f]);
+        a.foff[f] = rfl(p->foff[f]);
+    }
+    a.S = rflp(p->S);
+    a.offs = rflp(p->offs);
+    a.dI = rflp(p->dI);
+    a.ref = rflp(p->ref);
+    a.p1 = rfl(p->p1);
+    a.n_dirs = rfl(p->n_dirs);
+    for (int d = 0; d < 8; ++d) {
+        a.dirs[d] = rfl(p->dirs[d]);
+        a.out[d] = rflp(p->out[d]);
+    }
+    for (int d = 0; d < 9; ++d) a.path_begin[d] = rfl(p->path_begin[d]);
+    a.pg = 0;
+    return a;
+}
+
+// Persistent form over the paths of several frames: every wavefront takes
+// the next job (a path of some frame: jobs prefix[f] .. prefix[f + 1] - 1
+// are frame f's) from the counter until none is left, and loads the frame's
+// P2 table into its own LDS slice when the frame changes.  The counter
+// starts at 0 (the host clears it before the launch).
+template <int KP, int NF, bool WIN, bool SN>
+__global__ __launch_bounds__(64 * WAVES) void k_sgm_pk_jobs(const SgmArgs *__restrict__ list,
+                                                            const int *__restrict__ prefix, int n,
+                                                            unsigned *__restrict__ counter) {
+    __shared__ uint32_t lbuf[WAVES][2][PK_LW];
+    __shared__ int s_lut[WAVES][256];
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int total = rfl(prefix[n]);
+    int cur = -1;
+    for (;;) {
+        unsigned j = 0;
+        if (lane == 0) j = atomicAdd(counter, 1u);
+        const int job = __builtin_amdgcn_readfirstlane((int)j);
+        if (job >= total) break;
+        int f = 0;
+        while (f + 1 < n && job >= rfl(prefix[f + 1])) ++f;
+        if (f != cur) {
+            for (int i = lane; i < 256; i += 64) s_lut[wid][i] = list[f].lut[i];
+            __builtin_amdgcn_wave_barrier();
+            cur = f;
+        }
+        sgm_pk_path<KP, NF, WIN, SN, false>(uniform_sgm_args(list + f), job - rfl(prefix[f]), s_lut[wid], nullptr,
+                                            lbuf[wid][0], lbuf[wid][1]);
+    }
+}
+
 // Launch the two-label kernel for KP label pairs per lane (variant chosen
 // at run time).  Instantiated once per KP in k_sgm_inst.hip.
 template <int KP>
@@ -645,6 +732,31 @@ void sgm_launch_pk(const SgmArgs &a, bool win, bool sn, dim3 grid, hipStream_t s
     FMVS_SGMPK(false, false, true)
     FMVS_SGMPK(true, false, true)
 #undef FMVS_SGMPK
+}
+
+// The persistent form over several frames (no path gradient): nf_max bounds
+// the families of every frame (1 or up to 4).
+template <int KP>
+hipError_t sgm_launch_pk_jobs(const SgmArgs *list, const int *prefix, int n, unsigned *counter, bool win, bool sn,
+                              int nf_max, int blocks, hipStream_t s) {
+#define FMVS_SGMJ(W_, S_)                                                                                        \
+    if (win == W_ && sn == S_) {                                                                                \
+        if (nf_max == 1)                                                                                        \
+            hipLaunchKernelGGL((k_sgm_pk_jobs<KP, 1, W_, S_>), dim3(blocks), dim3(64 * WAVES), 0, s, list, prefix, \
+                               n, counter);                                                                     \
+        else if (nf_max <= 4)                                                                                   \
+            hipLaunchKernelGGL((k_sgm_pk_jobs<KP, 4, W_, S_>), dim3(blocks), dim3(64 * WAVES), 0, s, list, prefix, \
+                               n, counter);                                                                     \
+        else                                                                                                    \
+            return hipErrorInvalidValue;                                                                        \
+        return hipGetLastError();                                                                               \
+    }
+    FMVS_SGMJ(false, false)
+    FMVS_SGMJ(true, false)
+    FMVS_SGMJ(false, true)
+    FMVS_SGMJ(true, true)
+#undef FMVS_SGMJ
+    return hipErrorInvalidValue;
 }
 
 }  // namespace fmvs

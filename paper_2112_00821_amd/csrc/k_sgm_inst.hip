@@ -8,4 +8,6 @@
 
 namespace fmvs {
 template void sgm_launch_pk<FMVS_KP>(const SgmArgs &, bool, bool, dim3, hipStream_t);
+template hipError_t sgm_launch_pk_jobs<FMVS_KP>(const SgmArgs *, const int *, int, unsigned *, bool, bool, int, int,
+                                                hipStream_t);
 }  // namespace fmvs

@@ -58,20 +58,20 @@ __device__ __forceinline__ int combine_lr(int sL, int sR, int nL, int nR, int m)
 // (clamped) pixel-centre coordinates of every region sample (exact in
 // float), so the halo replicates the image border and a thread's sample i
 // is one LDS read at a fixed offset.
-template <int NS>
+// INSIDE: every sample of the region maps inside the view (the same value
+// without the border clamps, warp_sample_inside).
+template <int NS, bool INSIDE>
 __device__ __forceinline__ void warp_region(float *buf, const uint8_t *__restrict__ src, int w, int h,
                                             const float2 *tq, int tid, double h0, double h1, double h2, double h3,
                                             double h4, double h5, double h6, double h7, double h8) {
     constexpr int NFULL = NS / NT;
+    auto one = [&](const float2 q) {
+        return INSIDE ? warp_sample_inside(src, w, h, h0, h1, h2, h3, h4, h5, h6, h7, h8, (double)q.x, (double)q.y)
+                      : warp_sample(src, w, h, h0, h1, h2, h3, h4, h5, h6, h7, h8, (double)q.x, (double)q.y);
+    };
 #pragma unroll 2
-    for (int i = 0; i < NFULL; ++i) {
-        const float2 q = tq[tid + i * NT];
-        buf[tid + i * NT] = warp_sample(src, w, h, h0, h1, h2, h3, h4, h5, h6, h7, h8, (double)q.x, (double)q.y);
-    }
-    if (NS % NT != 0 && tid + NFULL * NT < NS) {
-        const float2 q = tq[tid + NFULL * NT];
-        buf[tid + NFULL * NT] = warp_sample(src, w, h, h0, h1, h2, h3, h4, h5, h6, h7, h8, (double)q.x, (double)q.y);
-    }
+    for (int i = 0; i < NFULL; ++i) buf[tid + i * NT] = one(tq[tid + i * NT]);
+    if (NS % NT != 0 && tid + NFULL * NT < NS) buf[tid + NFULL * NT] = one(tq[tid + NFULL * NT]);
 }
 }  // namespace
 
@@ -90,8 +90,17 @@ __device__ __forceinline__ int ncc_finish(int sA_i, int vA_i, double sB, double 
     return (int)floor(255.0 * c + 0.5);
 }
 
+// XCD-aware remap: hardware dispatches workgroup b to XCD b % 8; give each
+// XCD a contiguous range of logical work items.
+__device__ __forceinline__ int xcd_logical(int b, int nb) {
+    const int q = nb >> 3, r8 = nb & 7, xcd = b & 7, slot = b >> 3;
+    return xcd * q + min(xcd, r8) + slot;
+}
+
+// One workgroup's share of the sweep of one frame: logical = tile *
+// n_chunks + chunk.
 template <int CW, int CH, int RPT, bool WARPED, int COST>
-__global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
+__device__ __forceinline__ void sweep_block(const SweepArgs &a, const int logical) {
     constexpr int TH = 4 * RPT;
     constexpr int RX = CW / 2, RY = CH / 2;
     constexpr int RW = TW + 2 * RX, RH = TH + 2 * RY;
@@ -102,13 +111,8 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
     __shared__ double aref[COST == 1 ? NS : 1];   // reference intensities of the region (NCC)
     __shared__ float2 tq[NS];   // sample coordinates of the region
     __shared__ int s_lo[kMaxFam], s_hi[kMaxFam];
+    __shared__ int s_inside[2][kMaxViews];   // per plane (double-buffered) and view: region maps inside
 
-    // XCD-aware remap: hardware dispatches workgroup b to XCD b % 8; give
-    // each XCD a contiguous range of logical work items
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
-    const int q = nb >> 3, r8 = nb & 7, xcd = b & 7, slot = b >> 3;
-    const int logical = xcd * q + min(xcd, r8) + slot;
     const int chunk = logical % a.n_chunks;
     const int tile = logical / a.n_chunks;
     const int x0 = (tile % a.tiles_x) * TW;
@@ -128,6 +132,9 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
         tq[s2] = make_float2((float)min(max(x0 - RX + rx, 0), a.w - 1) + 0.5f,
                              (float)min(max(y0 - RY + ry, 0), a.h - 1) + 0.5f);
     }
+    // corners of the region's (clamped) sample points
+    const double qx_lo = (double)max(x0 - RX, 0) + 0.5, qx_hi = (double)min(x0 - RX + RW - 1, a.w - 1) + 0.5;
+    const double qy_lo = (double)max(y0 - RY, 0) + 0.5, qy_hi = (double)min(y0 - RY + RH - 1, a.h - 1) + 0.5;
     __syncthreads();
 
     uint32_t ref_hi[RPT], ref_lo[RPT];   // census cost: the reference census words
@@ -205,6 +212,29 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
 #pragma unroll
     for (int j = 0; j < RPT; ++j) acc[j] = 0;
 
+    // Whether each view's region maps inside the view for plane (f_, g_),
+    // into slot sl, by the first wave: lane 4k + c tests corner c of view k.
+    auto mark_inside = [&](int sl, int f_, int g_) {
+        if (WARPED || tid >= 64) return;
+        const int k = tid >> 2;
+        bool in = true;
+        if (k < a.n_views)
+            in = warp_corner_inside(a.H + ((size_t)k * a.sumG + a.goff[f_] + g_) * 9, tid & 3, qx_lo, qx_hi, qy_lo,
+                                    qy_hi, a.w, a.h);
+        const unsigned long long all = __ballot(in);
+        if (k < a.n_views && (tid & 3) == 0) s_inside[sl][k] = ((all >> (4 * k)) & 0xFull) == 0xFull;
+    };
+    // the plane after (f_, g_) in this block's order
+    auto next_plane = [&](int &f_, int &g_) {
+        if (++g_ >= s_hi[f_]) {
+            ++f_;
+            while (f_ < a.n_fam && s_hi[f_] <= s_lo[f_]) ++f_;
+            if (f_ < a.n_fam) g_ = s_lo[f_];
+        }
+    };
+    mark_inside(pos0 & 1, f, g);
+    __syncthreads();
+
     int it = 0;
     for (int pos = pos0; pos < pos1; ++pos) {
         // left-view sums in the low 16 bits, right-view sums in the high 16
@@ -228,8 +258,18 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
                 const double *Hm = a.H + hk * 9;
                 const double h0 = Hm[0], h1 = Hm[1], h2 = Hm[2], h3 = Hm[3], h4 = Hm[4], h5 = Hm[5], h6 = Hm[6],
                              h7 = Hm[7], h8 = Hm[8];
+                // the next plane's flags, while this plane's are read (that
+                // slot was last read before the previous barrier)
+                if (k == 0 && pos + 1 < pos1) {
+                    int fn = f, gn = g;
+                    next_plane(fn, gn);
+                    mark_inside((pos + 1) & 1, fn, gn);
+                }
                 const uint8_t *src = a.views[k];
-                warp_region<NS>(buf, src, a.w, a.h, tq, tid, h0, h1, h2, h3, h4, h5, h6, h7, h8);
+                if (s_inside[pos & 1][k])
+                    warp_region<NS, true>(buf, src, a.w, a.h, tq, tid, h0, h1, h2, h3, h4, h5, h6, h7, h8);
+                else
+                    warp_region<NS, false>(buf, src, a.w, a.h, tq, tid, h0, h1, h2, h3, h4, h5, h6, h7, h8);
             }
             __syncthreads();
             const uint32_t sh = a.side[k] < 0 ? 0u : 16u;
@@ -347,6 +387,23 @@ __global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
     }
 }
 
+template <int CW, int CH, int RPT, bool WARPED, int COST>
+__global__ __launch_bounds__(NT) void k_sweep(const SweepArgs a) {
+    sweep_block<CW, CH, RPT, WARPED, COST>(a, xcd_logical(blockIdx.x, gridDim.x));
+}
+
+// Several frames in one launch: the workgroups of frame f are the logical
+// items prefix[f] .. prefix[f + 1] - 1 (each frame's tiles x chunks), the
+// whole grid remapped to XCDs as one.
+template <int CW, int CH, int RPT, int COST>
+__global__ __launch_bounds__(NT) void k_sweep_batch(const SweepArgs *__restrict__ list,
+                                                    const int *__restrict__ prefix, int n) {
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    int f = 0;
+    while (f + 1 < n && logical >= prefix[f + 1]) ++f;
+    sweep_block<CW, CH, RPT, false, COST>(list[f], logical - prefix[f]);
+}
+
 // Launch one window size and cost: tiles of 64 x 4*rpt pixels (rpt 4 or 8),
 // from homographies or from pre-warped views.  Each (window, cost) pair is
 // instantiated in a translation unit of its own so the sweep variants
@@ -364,6 +421,16 @@ hipError_t sweep_launch_cfg(const SweepArgs &a, dim3 grid, int rpt, hipStream_t 
         else
             hipLaunchKernelGGL((k_sweep<CW, CH, 8, false, COST>), grid, dim3(NT), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+template <int CW, int CH, int COST>
+hipError_t sweep_launch_batch_cfg(const SweepArgs *list, const int *prefix, int n, int blocks, int rpt,
+                                  hipStream_t s) {
+    if (rpt == 4)
+        hipLaunchKernelGGL((k_sweep_batch<CW, CH, 4, COST>), dim3(blocks), dim3(NT), 0, s, list, prefix, n);
+    else
+        hipLaunchKernelGGL((k_sweep_batch<CW, CH, 8, COST>), dim3(blocks), dim3(NT), 0, s, list, prefix, n);
     return hipGetLastError();
 }
 

@@ -8,4 +8,6 @@
 
 namespace fmvs {
 template hipError_t sweep_launch_cfg<FMVS_CW, FMVS_CH, FMVS_COST>(const SweepArgs &, dim3, int, hipStream_t);
+template hipError_t sweep_launch_batch_cfg<FMVS_CW, FMVS_CH, FMVS_COST>(const SweepArgs *, const int *, int, int,
+                                                                        int, hipStream_t);
 }  // namespace fmvs

@@ -44,6 +44,10 @@ struct SweepArgs {
     unsigned long long *work; // optional counter of evaluated (pixel, label) pairs
 };
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t s);
+// several frames in one launch (see k_sweep.hip)
+size_t sweep_batch_bytes(int n);
+int prepare_sweep_batch(SweepArgs *host, int n, int rpt, int target, void *out);
+hipError_t launch_sweep_batch(const void *dev, int n, int blocks, int rpt, int cw, int ch, int cost, hipStream_t s);
 
 // ---------------------------------------------------------------- sgm
 struct SgmArgs {
@@ -78,6 +82,11 @@ struct SgmArgs {
 };
 int sgm_paths(int dir, int w, int h);
 hipError_t launch_sgm(const SgmArgs &a, hipStream_t s);
+// several frames' aggregation in one persistent launch (see k_sgm.hip)
+size_t sgm_batch_bytes(int n);
+int prepare_sgm_batch(SgmArgs *host, int n, void *out, int *kp, bool *win, bool *sn, int *nf_max);
+hipError_t launch_sgm_batch(const void *dev, int n, int jobs, int kp, bool win, bool sn, int nf_max,
+                            unsigned *counter, hipStream_t s);
 hipError_t launch_sum_u16(const uint16_t *const *bufs, int n, size_t count, uint16_t *out, hipStream_t s);
 
 // ---------------------------------------------------------------- image stages
@@ -117,8 +126,8 @@ struct SeedArgs {
     int cw, ch, fw, fh, n_fam;
     double Kinv[9];
     double fam_n[kMaxFam][3];
-    const double *delta;      // the fine level's plane lists, concatenated (device)
-    int goff[kMaxFam];        // first plane of each family in delta
+    const double *inv;        // the fine level's plane lists as inverse distances 1/delta, concatenated (device)
+    int goff[kMaxFam];        // first plane of each family in inv
     int G[kMaxFam], W[kMaxFam];
     const float *depth_c, *normal_c;
     float *dbar, *nbar;

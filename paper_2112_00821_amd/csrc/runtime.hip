@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -90,6 +91,7 @@ struct LevelPlan {
     bool windows = false, sn = false;
     size_t h_off = 0;   // offset (doubles) of this level's homographies in the parameter blob
     size_t d_off = 0;   // offset (doubles) of this level's plane lists
+    size_t i_off = 0;   // offset (doubles) of their inverse distances
 };
 
 struct FramePlan {
@@ -129,7 +131,29 @@ struct fassmvs_handle {
 
     // device buffers
     size_t held = 0;
+    uint64_t gen = 0;   // bumped whenever a device buffer moves (captured graphs then go stale)
     bool exact_growth = false;
+
+    // batched frames (fassmvs_submit_batch): one child handle per frame of
+    // the batch (own buffers and plan, this handle's stream)
+    std::vector<fassmvs_handle *> children;
+    int batch_n = 0;
+    bool batch_busy = false;
+    uint64_t batch_ticket = 0;
+    DevBuf batch_dev;                 // per-round argument blocks of the batched launches
+    void *batch_stage = nullptr;      // their pinned host copy
+    size_t batch_stage_bytes = 0;
+    struct BatchGraph {
+        hipGraphExec_t exec = nullptr;
+        uint64_t gen = 0;
+    };
+    std::map<std::string, BatchGraph> graphs;
+    struct Tuning {
+        int rpt = 8, target = 8192;
+        double ms = 0.0;
+    };
+    std::map<std::string, Tuning> tuned;
+    Tuning last_tuning;
     DevBuf pyr[kMaxViews + 1];       // every level of each image, level 0 first
     DevBuf ct, S, wta, c3, params, work_ctr;
     DevBuf sgmbuf[8];
@@ -196,6 +220,7 @@ fassmvs_status ensure(fassmvs_handle *h, DevBuf &b, size_t bytes) {
     }
     b.bytes = want;
     h->held += want;
+    h->gen++;
     return FASSMVS_OK;
 }
 
@@ -649,7 +674,8 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
     }
     for (int l = 0; l < c.n_levels; ++l) {
         P.lv[l].d_off = hsz + dsz;
-        dsz += P.lv[l].sumG;
+        P.lv[l].i_off = hsz + dsz + P.lv[l].sumG;
+        dsz += 2 * (size_t)P.lv[l].sumG;
     }
     P.blob.assign(hsz + dsz, 0.0);
     for (int l = 0; l < c.n_levels; ++l) {
@@ -664,6 +690,8 @@ fassmvs_status make_plan(fassmvs_handle *h, const fassmvs_image *ref, const fass
                 resample_list(top[f].data(), Gt, L.G[f], lst);
             for (int j = 1; j < L.G[f]; ++j)
                 if (!(lst[j] > lst[j - 1])) return fail(h, FASSMVS_EINVAL, "plane list too dense at a finer level");
+            double *inv = P.blob.data() + L.i_off + L.goff[f];
+            for (int j = 0; j < L.G[f]; ++j) inv[j] = 1.0 / lst[j];
             // inverse-distance step of a uniform list (path-gradient SGM)
             L.step[f] = (1.0 / lst[0] - 1.0 / lst[L.G[f] - 1]) / (double)(L.G[f] - 1);
         }
@@ -821,9 +849,21 @@ fassmvs_status run_sgm(fassmvs_handle *h, const LevelPlan &L, const uint8_t *S, 
     return FASSMVS_OK;
 }
 
-fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
-    const fassmvs_config &c = h->cfg;
-    double *dblob = (double *)h->params.p;
+// ---------------------------------------------------------------- the frame's steps
+// A frame runs as: pyramid; then per level, coarsest first: reference
+// census, sweep, aggregation (all directions), winner-takes-all,
+// refinement and the rest (median, normals, DoG mask, seeds of the next
+// level).  The single-frame path runs them in order; the batched path runs
+// each step for every frame of a round before the next, with the sweeps
+// and the aggregations of all frames in one launch each.
+
+size_t level_offset(const FramePlan &P, int l) {
+    size_t off = 0;
+    for (int i = 0; i < l; ++i) off += (size_t)P.lv[i].w * P.lv[i].h;
+    return off;
+}
+
+fassmvs_status enqueue_pyramid(fassmvs_handle *h, const FramePlan &P) {
     {
         Timer t(h, ST_PYR);
         for (int i = 0; i <= P.n_views; ++i) {
@@ -840,155 +880,248 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
     h->sweep_work = 0;
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, h->stream, (uint8_t *)h->work_ctr.p, (uint8_t)0, (size_t)8);
     HIPCHK(h, hipGetLastError(), "work counter");
-    size_t lvl_off[FASSMVS_MAX_LEVELS];
+    return FASSMVS_OK;
+}
+
+const uint8_t *level_ref(fassmvs_handle *h, const FramePlan &P, int l) {
+    return (const uint8_t *)h->pyr[0].p + level_offset(P, l);
+}
+
+fassmvs_status enqueue_census(fassmvs_handle *h, const FramePlan &P, int l) {
+    const fassmvs_config &c = h->cfg;
+    if (c.cost != 0) return FASSMVS_OK;
+    const LevelPlan &L = P.lv[l];
+    Timer t(h, ST_CENSUS);
+    HIPCHK(h, launch_census(level_ref(h, P, l), L.w, L.h, c.census_w, c.census_h, (uint64_t *)h->ct.p, h->stream),
+           "census");
+    return FASSMVS_OK;
+}
+
+SweepArgs sweep_args(fassmvs_handle *h, const FramePlan &P, int l) {
+    const fassmvs_config &c = h->cfg;
+    const LevelPlan &L = P.lv[l];
+    const size_t off = level_offset(P, l);
+    SweepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.w = L.w;
+    a.h = L.h;
+    a.cw = c.census_w;
+    a.ch = c.census_h;
+    a.n_views = P.n_views;
+    a.nL = P.nL;
+    a.nR = P.nR;
+    a.m = P.m;
+    for (int k = 0; k < P.n_views; ++k) {
+        a.views[k] = (const uint8_t *)h->pyr[k + 1].p + off;
+        a.side[k] = P.side[k];
+    }
+    a.cost = c.cost;
+    a.ct_ref = (const uint64_t *)h->ct.p;
+    a.ref = level_ref(h, P, l);
+    a.n_fam = L.F;
+    a.D = L.D;
+    a.sumG = L.sumG;
+    for (int f = 0; f < L.F; ++f) {
+        a.G[f] = L.G[f];
+        a.W[f] = L.W[f];
+        a.foff[f] = L.foff[f];
+        a.goff[f] = L.goff[f];
+    }
+    a.H = (const double *)h->params.p + L.h_off;
+    a.offs = L.windows ? (const int32_t *)h->lb[l].offs.p : nullptr;
+    a.S = (uint8_t *)h->S.p;
+    a.work = (unsigned long long *)h->work_ctr.p;
+    a.rows_per_thread = sweep_rows();
+    return a;
+}
+
+// The aggregation's arguments for every direction of the frame's level,
+// each into its own path-cost buffer.
+SgmArgs sgm_args(fassmvs_handle *h, const FramePlan &P, int l) {
+    const LevelPlan &L = P.lv[l];
+    SgmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.w = L.w;
+    a.h = L.h;
+    a.D = L.D;
+    a.n_fam = L.F;
+    for (int f = 0; f < L.F; ++f) {
+        a.W[f] = L.W[f];
+        a.foff[f] = L.foff[f];
+    }
+    a.S = (const uint8_t *)h->S.p;
+    a.offs = L.windows ? (const int32_t *)h->lb[l].offs.p : nullptr;
+    a.dI = L.sn ? (const int8_t *)h->lb[l].dI.p : nullptr;
+    a.ref = level_ref(h, P, l);
+    a.p1 = P.p1;
+    for (int i = 0; i < 256; ++i) a.lut[i] = P.lut[i];
+    a.n_dirs = h->cfg.n_paths;
+    for (int d = 0; d < a.n_dirs; ++d) {
+        a.dirs[d] = d;
+        a.out[d] = (uint16_t *)h->sgmbuf[d].p;
+    }
+    return a;
+}
+
+// Winner-takes-all over the level's path-cost buffers.
+fassmvs_status enqueue_wta(fassmvs_handle *h, const SgmArgs &dirs) {
+    Timer t(h, ST_SGM_WTA);
+    SgmArgs a = dirs;
+    a.n_dirs = 0;
+    a.n_in = h->cfg.n_paths;
+    for (int b = 0; b < a.n_in; ++b) a.in[b] = (uint16_t *)h->sgmbuf[b].p;
+    a.final_mode = 1;
+    a.wta = (uint16_t *)h->wta.p;
+    a.c3 = (uint16_t *)h->c3.p;
+    HIPCHK(h, launch_sgm(a, h->stream), "wta launch");
+    return FASSMVS_OK;
+}
+
+// Refinement, median, normals with confidence, the DoG mask at level 0, and
+// the seeds of the next finer level.
+fassmvs_status enqueue_post(fassmvs_handle *h, const FramePlan &P, int l) {
+    const fassmvs_config &c = h->cfg;
+    double *dblob = (double *)h->params.p;
+    const LevelPlan &L = P.lv[l];
+    const size_t N = (size_t)L.w * L.h;
+    auto &B = h->lb[l];
+    const uint8_t *ref = level_ref(h, P, l);
+    const int32_t *offs = L.windows ? (const int32_t *)B.offs.p : nullptr;
     {
-        size_t off = 0;
-        for (int l = 0; l < P.n_levels; ++l) {
-            lvl_off[l] = off;
-            off += (size_t)P.lv[l].w * P.lv[l].h;
+        Timer t(h, ST_REFINE);
+        RefineArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.w = L.w;
+        a.h = L.h;
+        a.n_fam = L.F;
+        for (int f = 0; f < L.F; ++f) {
+            a.W[f] = L.W[f];
+            a.G[f] = L.G[f];
+            a.foff[f] = L.foff[f];
+            a.goff[f] = L.goff[f];
+            for (int i = 0; i < 3; ++i) a.fam_n[f][i] = P.fam_n[f][i];
+        }
+        std::memcpy(a.Kinv, L.Kinv, sizeof(a.Kinv));
+        a.delta = dblob + L.d_off;
+        a.offs = offs;
+        a.wta = (const uint16_t *)h->wta.p;
+        a.c3 = (const uint16_t *)h->c3.p;
+        a.label = (int32_t *)B.label.p;
+        a.fam = (int32_t *)B.fam.p;
+        a.depth = (float *)(c.median ? B.depth_raw.p : B.depth.p);
+        HIPCHK(h, launch_refine(a, h->stream), "refine launch");
+    }
+    if (c.median) {
+        Timer t(h, ST_MEDIAN);
+        HIPCHK(h, launch_median5((const float *)B.depth_raw.p, L.w, L.h, (float *)B.depth.p, h->stream), "median");
+    }
+    {
+        Timer t(h, ST_NORMALS);
+        NormalArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.w = L.w;
+        a.h = L.h;
+        a.radius = c.normal_radius;
+        a.beta = c.normal_beta;
+        a.cos_rho = std::cos(c.conf_rho_deg * 3.14159265358979323846 / 180.0);
+        std::memcpy(a.Kinv, L.Kinv, sizeof(a.Kinv));
+        a.n_fam = L.F;
+        for (int f = 0; f < L.F; ++f)
+            for (int i = 0; i < 3; ++i) a.fam_n[f][i] = P.fam_n[f][i];
+        a.depth = (const float *)B.depth.p;
+        a.img = ref;
+        a.label = (const int32_t *)B.label.p;
+        a.fam = (const int32_t *)B.fam.p;
+        a.nraw = (float *)B.nraw.p;
+        a.normal = (float *)B.normal.p;
+        a.conf = (float *)B.conf.p;
+        HIPCHK(h, launch_normals(a, h->stream), "normals launch");
+    }
+    if (l == 0 && c.dog_filter) {
+        Timer t(h, ST_POST);
+        PostArgs pa = dog_args();
+        HIPCHK(h, launch_dog_mask(ref, L.w, L.h, pa, (double *)h->post_tmp.p, (uint8_t *)h->post_m0.p,
+                                  (uint8_t *)h->post_m1.p, h->stream),
+               "dog filter");
+        HIPCHK(h, launch_apply_keep((const uint8_t *)h->post_m1.p, N, (float *)B.depth.p, (float *)B.normal.p,
+                                    (float *)B.conf.p, h->stream),
+               "dog apply");
+    }
+    if (l > 0) {
+        Timer t(h, ST_SEED);
+        const LevelPlan &Lf = P.lv[l - 1];
+        auto &Bf = h->lb[l - 1];
+        SeedArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.cw = L.w;
+        a.ch = L.h;
+        a.fw = Lf.w;
+        a.fh = Lf.h;
+        a.n_fam = Lf.F;
+        std::memcpy(a.Kinv, Lf.Kinv, sizeof(a.Kinv));
+        for (int f = 0; f < Lf.F; ++f) {
+            for (int i = 0; i < 3; ++i) a.fam_n[f][i] = P.fam_n[f][i];
+            a.goff[f] = Lf.goff[f];
+            a.G[f] = Lf.G[f];
+            a.W[f] = Lf.W[f];
+        }
+        a.inv = dblob + Lf.i_off;
+        a.depth_c = (const float *)B.depth.p;
+        a.normal_c = (const float *)B.normal.p;
+        a.dbar = (float *)Bf.dbar.p;
+        a.nbar = (float *)Bf.nbar.p;
+        a.offs = (int32_t *)Bf.offs.p;
+        a.dI = Lf.sn ? (int8_t *)Bf.dI.p : nullptr;
+        HIPCHK(h, launch_seed(a, h->stream), "seed launch");
+    }
+    return FASSMVS_OK;
+}
+
+// Images to level 0 of each pyramid and the parameter blob to the device,
+// through the handle's pinned staging (host images) or device copies.
+fassmvs_status upload_frame(fassmvs_handle *h, const FramePlan &P, const fassmvs_image *ref,
+                            const fassmvs_image *views, int mem_kind) {
+    const size_t N0 = (size_t)P.w * P.h;
+    Timer t(h, ST_UPLOAD);
+    uint8_t *pin = (uint8_t *)h->pin;
+    for (int i = 0; i <= P.n_views; ++i) {
+        const fassmvs_image &im = i == 0 ? *ref : views[i - 1];
+        uint8_t *dst = (uint8_t *)h->pyr[i].p;
+        if (mem_kind == FASSMVS_MEM_HOST) {
+            uint8_t *stg = pin + N0 * i;
+            for (int y = 0; y < P.h; ++y) std::memcpy(stg + (size_t)y * P.w, im.pixels + (size_t)y * im.stride, P.w);
+            HIPCHK(h, hipMemcpyAsync(dst, stg, N0, hipMemcpyHostToDevice, h->stream), "image upload");
+        } else {
+            HIPCHK(h, hipMemcpy2DAsync(dst, P.w, im.pixels, im.stride, P.w, P.h, hipMemcpyDeviceToDevice, h->stream),
+                   "image copy");
         }
     }
+    double *pb = (double *)(pin + N0 * (P.n_views + 1) + 64 - ((uintptr_t)(pin + N0 * (P.n_views + 1)) & 63));
+    std::memcpy(pb, P.blob.data(), P.blob.size() * 8);
+    HIPCHK(h, hipMemcpyAsync(h->params.p, pb, P.blob.size() * 8, hipMemcpyHostToDevice, h->stream), "params");
+    return FASSMVS_OK;
+}
+
+fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
+    const fassmvs_config &c = h->cfg;
+    fassmvs_status st;
+    if ((st = enqueue_pyramid(h, P)) != FASSMVS_OK) return st;
     for (int l = P.n_levels - 1; l >= 0; --l) {
         const LevelPlan &L = P.lv[l];
-        const size_t N = (size_t)L.w * L.h;
-        auto &B = h->lb[l];
-        const uint8_t *ref = (const uint8_t *)h->pyr[0].p + lvl_off[l];
-        if (c.cost == 0) {
-            Timer t(h, ST_CENSUS);
-            HIPCHK(h, launch_census(ref, L.w, L.h, c.census_w, c.census_h, (uint64_t *)h->ct.p, h->stream), "census");
-        }
-        const int32_t *offs = L.windows ? (const int32_t *)B.offs.p : nullptr;
-        const int8_t *dI = L.sn ? (const int8_t *)B.dI.p : nullptr;
+        if ((st = enqueue_census(h, P, l)) != FASSMVS_OK) return st;
         {
             Timer t(h, ST_SWEEP);
-            SweepArgs a;
-            std::memset(&a, 0, sizeof(a));
-            a.w = L.w;
-            a.h = L.h;
-            a.cw = c.census_w;
-            a.ch = c.census_h;
-            a.n_views = P.n_views;
-            a.nL = P.nL;
-            a.nR = P.nR;
-            a.m = P.m;
-            for (int k = 0; k < P.n_views; ++k) {
-                a.views[k] = (const uint8_t *)h->pyr[k + 1].p + lvl_off[l];
-                a.side[k] = P.side[k];
-            }
-            a.cost = c.cost;
-            a.ct_ref = (const uint64_t *)h->ct.p;
-            a.ref = ref;
-            a.n_fam = L.F;
-            a.D = L.D;
-            a.sumG = L.sumG;
-            for (int f = 0; f < L.F; ++f) {
-                a.G[f] = L.G[f];
-                a.W[f] = L.W[f];
-                a.foff[f] = L.foff[f];
-                a.goff[f] = L.goff[f];
-            }
-            a.H = dblob + L.h_off;
-            a.offs = offs;
-            a.S = (uint8_t *)h->S.p;
-            a.work = (unsigned long long *)h->work_ctr.p;
-            a.rows_per_thread = sweep_rows();
-            HIPCHK(h, launch_sweep(a, h->stream), "sweep launch");
+            HIPCHK(h, launch_sweep(sweep_args(h, P, l), h->stream), "sweep launch");
         }
+        const SgmArgs sa = sgm_args(h, P, l);
         uint16_t *bufs[8];
         for (int i = 0; i < 8; ++i) bufs[i] = (uint16_t *)h->sgmbuf[i].p;
-        PgGeom pgg{dblob + L.d_off, P.fam_n};
-        fassmvs_status st = run_sgm(h, L, (const uint8_t *)h->S.p, offs, dI, ref, P.p1, P.lut, c.n_paths, bufs,
-                                    c.sgm_debug ? (uint16_t *)h->sbar.p : nullptr, (uint16_t *)h->wta.p,
-                                    (uint16_t *)h->c3.p, c.sgm_variant == 2 ? &pgg : nullptr);
+        PgGeom pgg{(const double *)h->params.p + L.d_off, P.fam_n};
+        st = run_sgm(h, L, sa.S, sa.offs, sa.dI, sa.ref, P.p1, P.lut, c.n_paths, bufs,
+                     c.sgm_debug ? (uint16_t *)h->sbar.p : nullptr, (uint16_t *)h->wta.p, (uint16_t *)h->c3.p,
+                     c.sgm_variant == 2 ? &pgg : nullptr);
         if (st != FASSMVS_OK) return st;
-        {
-            Timer t(h, ST_REFINE);
-            RefineArgs a;
-            std::memset(&a, 0, sizeof(a));
-            a.w = L.w;
-            a.h = L.h;
-            a.n_fam = L.F;
-            for (int f = 0; f < L.F; ++f) {
-                a.W[f] = L.W[f];
-                a.G[f] = L.G[f];
-                a.foff[f] = L.foff[f];
-                a.goff[f] = L.goff[f];
-                for (int i = 0; i < 3; ++i) a.fam_n[f][i] = P.fam_n[f][i];
-            }
-            std::memcpy(a.Kinv, L.Kinv, sizeof(a.Kinv));
-            a.delta = dblob + L.d_off;
-            a.offs = offs;
-            a.wta = (const uint16_t *)h->wta.p;
-            a.c3 = (const uint16_t *)h->c3.p;
-            a.label = (int32_t *)B.label.p;
-            a.fam = (int32_t *)B.fam.p;
-            a.depth = (float *)(c.median ? B.depth_raw.p : B.depth.p);
-            HIPCHK(h, launch_refine(a, h->stream), "refine launch");
-        }
-        if (c.median) {
-            Timer t(h, ST_MEDIAN);
-            HIPCHK(h, launch_median5((const float *)B.depth_raw.p, L.w, L.h, (float *)B.depth.p, h->stream), "median");
-        }
-        {
-            Timer t(h, ST_NORMALS);
-            NormalArgs a;
-            std::memset(&a, 0, sizeof(a));
-            a.w = L.w;
-            a.h = L.h;
-            a.radius = c.normal_radius;
-            a.beta = c.normal_beta;
-            a.cos_rho = std::cos(c.conf_rho_deg * 3.14159265358979323846 / 180.0);
-            std::memcpy(a.Kinv, L.Kinv, sizeof(a.Kinv));
-            a.n_fam = L.F;
-            for (int f = 0; f < L.F; ++f)
-                for (int i = 0; i < 3; ++i) a.fam_n[f][i] = P.fam_n[f][i];
-            a.depth = (const float *)B.depth.p;
-            a.img = ref;
-            a.label = (const int32_t *)B.label.p;
-            a.fam = (const int32_t *)B.fam.p;
-            a.nraw = (float *)B.nraw.p;
-            a.normal = (float *)B.normal.p;
-            a.conf = (float *)B.conf.p;
-            HIPCHK(h, launch_normals(a, h->stream), "normals launch");
-        }
-        if (l == 0 && c.dog_filter) {
-            Timer t(h, ST_POST);
-            PostArgs pa = dog_args();
-            HIPCHK(h, launch_dog_mask(ref, L.w, L.h, pa, (double *)h->post_tmp.p, (uint8_t *)h->post_m0.p,
-                                      (uint8_t *)h->post_m1.p, h->stream),
-                   "dog filter");
-            HIPCHK(h, launch_apply_keep((const uint8_t *)h->post_m1.p, N, (float *)B.depth.p, (float *)B.normal.p,
-                                        (float *)B.conf.p, h->stream),
-                   "dog apply");
-        }
-        if (l > 0) {
-            Timer t(h, ST_SEED);
-            const LevelPlan &Lf = P.lv[l - 1];
-            auto &Bf = h->lb[l - 1];
-            SeedArgs a;
-            std::memset(&a, 0, sizeof(a));
-            a.cw = L.w;
-            a.ch = L.h;
-            a.fw = Lf.w;
-            a.fh = Lf.h;
-            a.n_fam = Lf.F;
-            std::memcpy(a.Kinv, Lf.Kinv, sizeof(a.Kinv));
-            for (int f = 0; f < Lf.F; ++f) {
-                for (int i = 0; i < 3; ++i) a.fam_n[f][i] = P.fam_n[f][i];
-                a.goff[f] = Lf.goff[f];
-                a.G[f] = Lf.G[f];
-                a.W[f] = Lf.W[f];
-            }
-            a.delta = dblob + Lf.d_off;
-            a.depth_c = (const float *)B.depth.p;
-            a.normal_c = (const float *)B.normal.p;
-            a.dbar = (float *)Bf.dbar.p;
-            a.nbar = (float *)Bf.nbar.p;
-            a.offs = (int32_t *)Bf.offs.p;
-            a.dI = Lf.sn ? (int8_t *)Bf.dI.p : nullptr;
-            HIPCHK(h, launch_seed(a, h->stream), "seed launch");
-        }
-        (void)N;
+        if ((st = enqueue_post(h, P, l)) != FASSMVS_OK) return st;
     }
     return FASSMVS_OK;
 }
@@ -998,6 +1131,174 @@ fassmvs_status copy_out(fassmvs_handle *h, void *dst, const void *src, size_t by
     hipMemcpyKind k = mem_kind == FASSMVS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     HIPCHK(h, hipMemcpyAsync(dst, src, bytes, k, h->stream), "output copy");
     return FASSMVS_OK;
+}
+
+// ---------------------------------------------------------------- batched frames
+// One round of a batch: frame i at its level levels[i] (rounds run from the
+// coarsest level of every frame down, frames with fewer levels finish
+// early), its sweeps in one launch and its aggregations in one persistent
+// launch.
+struct BatchRound {
+    std::vector<int> frames, levels;
+    size_t sweep_off = 0, sgm_off = 0;
+    int sweep_blocks = 0;
+    int sgm_jobs = -1;   // -1: the frames' aggregations run one launch each
+    int kp = 1, nf = 1;
+    bool win = false, sn = false;
+};
+
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxBatchGraphs = 8;   // captured batch graphs kept per handle
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// The batch's shape: sizes, view split, plane counts and windows of every
+// frame and level.  With values, also what the per-frame launches take by
+// value (intrinsics, plane normals, list steps, penalties), so that a
+// captured graph is replayed only for frames that agree in all of it.
+std::string batch_signature(fassmvs_handle *h, int n, int rpt, int target, bool values) {
+    std::string sig = std::to_string(rpt) + "/" + std::to_string(target);
+    auto raw = [&sig](const void *p, size_t b) { sig.append((const char *)p, b); };
+    for (int i = 0; i < n; ++i) {
+        const FramePlan &P = h->children[i]->plan;
+        sig += "|" + std::to_string(P.w) + "x" + std::to_string(P.h) + "v" + std::to_string(P.nL) + "," +
+               std::to_string(P.nR) + "F" + std::to_string(P.F);
+        for (int l = 0; l < P.n_levels; ++l) {
+            const LevelPlan &L = P.lv[l];
+            sig += ":" + std::to_string(L.D) + "/" + std::to_string(L.sumG) + (L.windows ? "w" : "") +
+                   (L.sn ? "s" : "");
+            if (values) {
+                raw(L.Kinv, sizeof(L.Kinv));
+                raw(L.step, sizeof(double) * L.F);
+                raw(L.G, sizeof(int) * L.F);
+                raw(L.W, sizeof(int) * L.F);
+            }
+        }
+        if (values) {
+            raw(P.fam_n, sizeof(double) * 3 * P.F);
+            raw(&P.p1, sizeof(P.p1));
+            raw(P.lut, sizeof(P.lut));
+        }
+    }
+    return sig;
+}
+
+// Every round's argument blocks into the pinned stage (grown as needed);
+// *bytes receives their size, the counter of the persistent aggregation
+// sitting at its end.
+fassmvs_status batch_prepare(fassmvs_handle *h, int n, int rpt, int target, std::vector<BatchRound> &rounds,
+                             size_t *bytes) {
+    int R = 0;
+    for (int i = 0; i < n; ++i) R = std::max(R, h->children[i]->plan.n_levels);
+    rounds.assign(R, BatchRound());
+    size_t off = 0;
+    for (int r = 0; r < R; ++r) {
+        BatchRound &br = rounds[r];
+        for (int i = 0; i < n; ++i) {
+            const int l = h->children[i]->plan.n_levels - 1 - r;
+            if (l < 0) continue;
+            br.frames.push_back(i);
+            br.levels.push_back(l);
+        }
+        br.sweep_off = off;
+        off = align_up(off + sweep_batch_bytes((int)br.frames.size()));
+        br.sgm_off = off;
+        off = align_up(off + sgm_batch_bytes((int)br.frames.size()));
+    }
+    const size_t total = off + kAlign;
+    if (h->batch_stage_bytes < total) {
+        if (h->batch_stage) hipHostFree(h->batch_stage);
+        h->batch_stage = nullptr;
+        h->batch_stage_bytes = 0;
+        if (hipHostMalloc(&h->batch_stage, total) != hipSuccess) {
+            (void)hipGetLastError();
+            h->batch_stage = nullptr;
+            return fail(h, FASSMVS_ENOMEM, "pinned batch staging allocation failed");
+        }
+        h->batch_stage_bytes = total;
+    }
+    for (auto &br : rounds) {
+        const int m = (int)br.frames.size();
+        std::vector<SweepArgs> sw(m);
+        std::vector<SgmArgs> sg(m);
+        for (int j = 0; j < m; ++j) {
+            fassmvs_handle *c = h->children[br.frames[j]];
+            sw[j] = sweep_args(c, c->plan, br.levels[j]);
+            sg[j] = sgm_args(c, c->plan, br.levels[j]);
+        }
+        br.sweep_blocks = prepare_sweep_batch(sw.data(), m, rpt, target, (uint8_t *)h->batch_stage + br.sweep_off);
+        if (br.sweep_blocks < 0) return fail(h, FASSMVS_EINVAL, "frames of a batch must share the matching cost");
+        // the path-gradient form and the debug sums run frame by frame
+        br.sgm_jobs = (h->cfg.sgm_debug || h->cfg.sgm_variant == 2)
+                          ? -1
+                          : prepare_sgm_batch(sg.data(), m, (uint8_t *)h->batch_stage + br.sgm_off, &br.kp,
+                                              &br.win, &br.sn, &br.nf);
+    }
+    *bytes = total;
+    return FASSMVS_OK;
+}
+
+// The batch's launches, all on the handle's stream (kernels only, so the
+// sequence can be captured in a graph).  With ev (two events per round) the
+// sweeps are timed.
+fassmvs_status batch_enqueue(fassmvs_handle *h, int n, const std::vector<BatchRound> &rounds, int rpt,
+                             size_t counter_off, hipEvent_t *ev) {
+    const fassmvs_config &c = h->cfg;
+    fassmvs_status st;
+    for (int i = 0; i < n; ++i)
+        if ((st = enqueue_pyramid(h->children[i], h->children[i]->plan)) != FASSMVS_OK) return st;
+    uint8_t *dev = (uint8_t *)h->batch_dev.p;
+    unsigned *counter = (unsigned *)(dev + counter_off);
+    for (size_t r = 0; r < rounds.size(); ++r) {
+        const BatchRound &br = rounds[r];
+        const int m = (int)br.frames.size();
+        for (int j = 0; j < m; ++j) {
+            fassmvs_handle *ch = h->children[br.frames[j]];
+            if ((st = enqueue_census(ch, ch->plan, br.levels[j])) != FASSMVS_OK) return fail(h, st, ch->err);
+        }
+        if (ev) HIPCHK(h, hipEventRecord(ev[2 * r], h->stream), "timing event");
+        HIPCHK(h, launch_sweep_batch(dev + br.sweep_off, m, br.sweep_blocks, rpt, c.census_w, c.census_h, c.cost,
+                                     h->stream),
+               "batched sweep launch");
+        if (ev) HIPCHK(h, hipEventRecord(ev[2 * r + 1], h->stream), "timing event");
+        if (br.sgm_jobs >= 0) {
+            HIPCHK(h, launch_sgm_batch(dev + br.sgm_off, m, br.sgm_jobs, br.kp, br.win, br.sn, br.nf, counter,
+                                       h->stream),
+                   "batched aggregation launch");
+        }
+        for (int j = 0; j < m; ++j) {
+            fassmvs_handle *ch = h->children[br.frames[j]];
+            const FramePlan &P = ch->plan;
+            const int l = br.levels[j];
+            const SgmArgs sa = sgm_args(ch, P, l);
+            if (br.sgm_jobs < 0) {
+                uint16_t *bufs[8];
+                for (int i = 0; i < 8; ++i) bufs[i] = (uint16_t *)ch->sgmbuf[i].p;
+                PgGeom pgg{(const double *)ch->params.p + P.lv[l].d_off, P.fam_n};
+                st = run_sgm(ch, P.lv[l], sa.S, sa.offs, sa.dI, sa.ref, P.p1, P.lut, c.n_paths, bufs,
+                             c.sgm_debug ? (uint16_t *)ch->sbar.p : nullptr, (uint16_t *)ch->wta.p,
+                             (uint16_t *)ch->c3.p, c.sgm_variant == 2 ? &pgg : nullptr);
+                if (st != FASSMVS_OK) return fail(h, st, ch->err);
+            } else if ((st = enqueue_wta(ch, sa)) != FASSMVS_OK) {
+                return fail(h, st, ch->err);
+            }
+            if ((st = enqueue_post(ch, P, l)) != FASSMVS_OK) return fail(h, st, ch->err);
+        }
+    }
+    return FASSMVS_OK;
+}
+
+fassmvs_status batch_upload_args(fassmvs_handle *h, size_t bytes) {
+    if (h->batch_dev.bytes < bytes) {
+        fassmvs_status st = ensure(h, h->batch_dev, bytes);
+        if (st != FASSMVS_OK) return st;
+    }
+    HIPCHK(h, hipMemcpyAsync(h->batch_dev.p, h->batch_stage, bytes, hipMemcpyHostToDevice, h->stream), "batch args");
+    return FASSMVS_OK;
+}
+
+bool env_off(const char *name) {
+    const char *e = std::getenv(name);
+    return e && std::atoi(e) == 0;
 }
 
 }  // namespace
@@ -1025,7 +1326,7 @@ fassmvs_status fassmvs_frame_footprint(const fassmvs_config *cfg, int32_t w, int
             const size_t G = count << (cfg->n_levels - 1 - l);
             const bool windows = l < cfg->n_levels - 1 && cfg->window_labels > 0;
             D += windows ? std::min((size_t)cfg->window_labels, G) : G;
-            params += G * ((size_t)n_views * 9 + 1) * 8;   // homographies and the plane list
+            params += G * ((size_t)n_views * 9 + 2) * 8;   // homographies, the plane list and its inverses
         }
         const size_t N = (size_t)lw * lh;
         NDmax = std::max(NDmax, N * D);
@@ -1165,7 +1466,7 @@ fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref,
     if (!h) return FASSMVS_EINVAL;
     std::lock_guard<std::mutex> lk(h->mu);
     if (h->latched) return FASSMVS_EDEVICE;
-    if (h->busy) return fail(h, FASSMVS_EBUSY, "a frame is in flight; poll it first");
+    if (h->busy || h->batch_busy) return fail(h, FASSMVS_EBUSY, "a frame is in flight; poll it first");
     if (!ticket) return fail(h, FASSMVS_EINVAL, "null ticket");
     if (mem_kind != FASSMVS_MEM_HOST && mem_kind != FASSMVS_MEM_DEVICE) return fail(h, FASSMVS_EINVAL, "bad mem_kind");
     HIPCHK(h, hipSetDevice(h->cfg.device), "hipSetDevice");
@@ -1173,27 +1474,7 @@ fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref,
     fassmvs_status st = make_plan(h, ref, views, view_side, n_views, K, families, n_families, P);
     if (st != FASSMVS_OK) return st;
     if ((st = alloc_frame(h, P)) != FASSMVS_OK) return st;
-    const size_t N0 = (size_t)P.w * P.h;
-    {
-        Timer t(h, ST_UPLOAD);
-        // images -> level 0 of each pyramid
-        uint8_t *pin = (uint8_t *)h->pin;
-        for (int i = 0; i <= P.n_views; ++i) {
-            const fassmvs_image &im = i == 0 ? *ref : views[i - 1];
-            uint8_t *dst = (uint8_t *)h->pyr[i].p;
-            if (mem_kind == FASSMVS_MEM_HOST) {
-                uint8_t *stg = pin + N0 * i;
-                for (int y = 0; y < P.h; ++y) std::memcpy(stg + (size_t)y * P.w, im.pixels + (size_t)y * im.stride, P.w);
-                HIPCHK(h, hipMemcpyAsync(dst, stg, N0, hipMemcpyHostToDevice, h->stream), "image upload");
-            } else {
-                HIPCHK(h, hipMemcpy2DAsync(dst, P.w, im.pixels, im.stride, P.w, P.h, hipMemcpyDeviceToDevice, h->stream),
-                       "image copy");
-            }
-        }
-        double *pb = (double *)(pin + N0 * (P.n_views + 1) + 64 - ((uintptr_t)(pin + N0 * (P.n_views + 1)) & 63));
-        std::memcpy(pb, P.blob.data(), P.blob.size() * 8);
-        HIPCHK(h, hipMemcpyAsync(h->params.p, pb, P.blob.size() * 8, hipMemcpyHostToDevice, h->stream), "params");
-    }
+    if ((st = upload_frame(h, P, ref, views, mem_kind)) != FASSMVS_OK) return st;
     if ((st = enqueue_frame(h, P)) != FASSMVS_OK) return st;
     HIPCHK(h, hipMemcpyAsync(h->work_host, h->work_ctr.p, 8, hipMemcpyDeviceToHost, h->stream), "work counter");
     HIPCHK(h, hipEventRecord(h->done, h->stream), "event record");
@@ -1202,6 +1483,175 @@ fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref,
     h->busy = true;
     h->ticket = h->next_ticket++;
     *ticket = h->ticket;
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_submit_batch(fassmvs_handle *h, const fassmvs_frame *frames, int32_t n_frames, int32_t mem_kind,
+                                    uint64_t *ticket) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (h->latched) return FASSMVS_EDEVICE;
+    if (h->busy || h->batch_busy) return fail(h, FASSMVS_EBUSY, "a frame or batch is in flight; poll it first");
+    if (!ticket || !frames || n_frames < 1 || n_frames > FASSMVS_MAX_BATCH)
+        return fail(h, FASSMVS_EINVAL, "a batch holds 1..64 frames");
+    if (mem_kind != FASSMVS_MEM_HOST && mem_kind != FASSMVS_MEM_DEVICE) return fail(h, FASSMVS_EINVAL, "bad mem_kind");
+    HIPCHK(h, hipSetDevice(h->cfg.device), "hipSetDevice");
+    // one child handle per frame: its own plan and buffers, this stream
+    while ((int)h->children.size() < n_frames) {
+        fassmvs_config cc = h->cfg;
+        cc.stream = h->stream;
+        cc.profile = 0;
+        fassmvs_handle *ch = nullptr;
+        fassmvs_status st = fassmvs_create(&cc, &ch);
+        if (st != FASSMVS_OK) return fail(h, st, "batch slot: " + g_create_error);
+        h->children.push_back(ch);
+    }
+    for (int i = 0; i < n_frames; ++i) {
+        const fassmvs_frame &fr = frames[i];
+        fassmvs_handle *ch = h->children[i];
+        ch->cfg = h->cfg;
+        ch->cfg.stream = h->stream;
+        ch->cfg.profile = 0;
+        if (fr.n_levels != 0) ch->cfg.n_levels = fr.n_levels;
+        if (fr.window_labels >= 0) ch->cfg.window_labels = fr.window_labels;
+        if (ch->cfg.n_levels < 1 || ch->cfg.n_levels > FASSMVS_MAX_LEVELS)
+            return fail(h, FASSMVS_EINVAL, "frame " + std::to_string(i) + ": n_levels must be 1..5");
+        fassmvs_status st = make_plan(ch, fr.ref, fr.views, fr.view_side, fr.n_views, fr.K, fr.families,
+                                      fr.n_families, ch->plan);
+        if (st != FASSMVS_OK) return fail(h, st, "frame " + std::to_string(i) + ": " + ch->err);
+        if ((st = alloc_frame(ch, ch->plan)) != FASSMVS_OK) return fail(h, st, "frame " + std::to_string(i) + ": " + ch->err);
+    }
+    const bool use_graph = !env_off("FASSMVS_BATCH_GRAPH"), tune = !env_off("FASSMVS_BATCH_TUNE");
+    // the sweep's tile height and workgroup target: tuned once per batch shape
+    // (neither changes a result)
+    std::string shape = batch_signature(h, n_frames, 0, 0, false);
+    auto tit = h->tuned.find(shape);
+    fassmvs_status st;
+    for (int i = 0; i < n_frames; ++i) {
+        const fassmvs_frame &fr = frames[i];
+        if ((st = upload_frame(h->children[i], h->children[i]->plan, fr.ref, fr.views, mem_kind)) != FASSMVS_OK)
+            return fail(h, st, h->children[i]->err);
+    }
+    std::vector<BatchRound> rounds;
+    size_t bytes = 0;
+    if (tit == h->tuned.end() && tune) {
+        // time the batch once per candidate (the sweeps, HIP events), keep the fastest
+        static const int kRpt[] = {8, 4};
+        static const int kTarget[] = {4096, 8192, 16384};
+        fassmvs_handle::Tuning best;
+        best.ms = 1e30;
+        std::vector<hipEvent_t> ev;
+        for (int rpt : kRpt)
+            for (int target : kTarget) {
+                if ((st = batch_prepare(h, n_frames, rpt, target, rounds, &bytes)) != FASSMVS_OK) return st;
+                if ((st = batch_upload_args(h, bytes)) != FASSMVS_OK) return st;
+                while (ev.size() < 2 * rounds.size()) {
+                    hipEvent_t e;
+                    HIPCHK(h, hipEventCreate(&e), "timing event");
+                    ev.push_back(e);
+                }
+                if ((st = batch_enqueue(h, n_frames, rounds, rpt, bytes - kAlign, ev.data())) != FASSMVS_OK) return st;
+                HIPCHK(h, hipStreamSynchronize(h->stream), "batch tuning run");
+                double ms = 0.0;
+                for (size_t r = 0; r < rounds.size(); ++r) {
+                    float t = 0.0f;
+                    HIPCHK(h, hipEventElapsedTime(&t, ev[2 * r], ev[2 * r + 1]), "timing");
+                    ms += t;
+                }
+                if (ms < best.ms) best = fassmvs_handle::Tuning{rpt, target, ms};
+            }
+        for (auto e : ev) hipEventDestroy(e);
+        tit = h->tuned.emplace(shape, fassmvs_handle::Tuning{best.rpt, best.target, best.ms}).first;
+    }
+    const int rpt = tit != h->tuned.end() ? tit->second.rpt : 8;
+    const int target = tit != h->tuned.end() ? tit->second.target : 8192;
+    if (tit != h->tuned.end()) h->last_tuning = tit->second;
+    if ((st = batch_prepare(h, n_frames, rpt, target, rounds, &bytes)) != FASSMVS_OK) return st;
+    if ((st = batch_upload_args(h, bytes)) != FASSMVS_OK) return st;
+    if (use_graph) {
+        uint64_t gen = h->gen;
+        for (int i = 0; i < n_frames; ++i) gen += h->children[i]->gen;
+        const std::string key = batch_signature(h, n_frames, rpt, target, true);
+        if (h->graphs.size() >= kMaxBatchGraphs && !h->graphs.count(key)) {
+            for (auto &kv : h->graphs)
+                if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+            h->graphs.clear();
+        }
+        auto &g = h->graphs[key];
+        if (!g.exec || g.gen != gen) {
+            if (g.exec) hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+            // the launches of the whole batch, captured once and replayed while
+            // the shape and the buffers stay
+            HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed), "graph capture");
+            st = batch_enqueue(h, n_frames, rounds, rpt, bytes - kAlign, nullptr);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(h->stream, &graph);
+            if (st != FASSMVS_OK) {
+                if (graph) hipGraphDestroy(graph);
+                return st;
+            }
+            HIPCHK(h, e, "graph capture");
+            e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            HIPCHK(h, e, "graph instantiation");
+            g.gen = gen;
+        }
+        HIPCHK(h, hipGraphLaunch(g.exec, h->stream), "graph launch");
+    } else if ((st = batch_enqueue(h, n_frames, rounds, rpt, bytes - kAlign, nullptr)) != FASSMVS_OK) {
+        return st;
+    }
+    HIPCHK(h, hipEventRecord(h->done, h->stream), "event record");
+    h->batch_n = n_frames;
+    h->batch_busy = true;
+    h->batch_ticket = h->next_ticket++;
+    *ticket = h->batch_ticket;
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_poll_batch(fassmvs_handle *h, uint64_t ticket, int32_t index, float *depth, float *normal,
+                                  float *confidence, int32_t mem_kind, int32_t wait_ms) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (h->latched) return FASSMVS_EDEVICE;
+    if (ticket == 0 || ticket != h->batch_ticket) return fail(h, FASSMVS_ENOTFOUND, "unknown batch ticket");
+    if (index < 0 || index >= h->batch_n) return fail(h, FASSMVS_EINVAL, "frame index outside the batch");
+    if (mem_kind != FASSMVS_MEM_HOST && mem_kind != FASSMVS_MEM_DEVICE) return fail(h, FASSMVS_EINVAL, "bad mem_kind");
+    HIPCHK(h, hipSetDevice(h->cfg.device), "hipSetDevice");
+    if (h->batch_busy) {
+        auto t0 = std::chrono::steady_clock::now();
+        for (;;) {
+            hipError_t e = hipEventQuery(h->done);
+            if (e == hipSuccess) break;
+            if (e != hipErrorNotReady) return dev_fail(h, e, "batch execution");
+            if (wait_ms == 0) return FASSMVS_PENDING;
+            if (wait_ms < 0) {
+                HIPCHK(h, hipEventSynchronize(h->done), "batch execution");
+                break;
+            }
+            double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (el >= wait_ms) return FASSMVS_PENDING;
+            std::this_thread::sleep_for(std::chrono::microseconds(200));
+        }
+        h->batch_busy = false;
+    }
+    fassmvs_handle *ch = h->children[index];
+    const size_t N0 = (size_t)ch->plan.w * ch->plan.h;
+    auto &B = ch->lb[0];
+    fassmvs_status st;
+    if ((st = copy_out(h, depth, B.depth.p, N0 * 4, mem_kind)) != FASSMVS_OK) return st;
+    if ((st = copy_out(h, normal, B.normal.p, N0 * 12, mem_kind)) != FASSMVS_OK) return st;
+    if ((st = copy_out(h, confidence, B.conf.p, N0 * 4, mem_kind)) != FASSMVS_OK) return st;
+    HIPCHK(h, hipStreamSynchronize(h->stream), "output copy");
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_batch_tuning(fassmvs_handle *h, int32_t *rows_per_thread, int32_t *sweep_blocks, double *ms) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (rows_per_thread) *rows_per_thread = h->last_tuning.rpt;
+    if (sweep_blocks) *sweep_blocks = h->last_tuning.target;
+    if (ms) *ms = h->last_tuning.ms;
     return FASSMVS_OK;
 }
 
@@ -1249,6 +1699,7 @@ void handle_trim(fassmvs_handle *h) {
         h->held -= b.bytes;
         b = DevBuf();
     };
+    h->gen++;
     for (auto &b : h->pyr) drop(b);
     drop(h->ct);
     drop(h->S);
@@ -1321,6 +1772,9 @@ void fassmvs_destroy(fassmvs_handle *h) {
         std::lock_guard<std::mutex> lk(h->mu);
         hipSetDevice(h->cfg.device);
         hipStreamSynchronize(h->stream);
+        // batch slots share this stream: released before it
+        for (auto *c : h->children) fassmvs_destroy(c);
+        h->children.clear();
         for (auto &b : h->pyr) release(b);
         release(h->ct);
         release(h->S);
@@ -1334,6 +1788,10 @@ void fassmvs_destroy(fassmvs_handle *h) {
             release(L.depth_raw); release(L.depth); release(L.nraw); release(L.normal); release(L.conf);
             release(L.label); release(L.fam); release(L.offs); release(L.dI); release(L.dbar); release(L.nbar);
         }
+        for (auto &g : h->graphs)
+            if (g.second.exec) hipGraphExecDestroy(g.second.exec);
+        release(h->batch_dev);
+        if (h->batch_stage) hipHostFree(h->batch_stage);
         if (h->pin) hipHostFree(h->pin);
         if (h->work_host) hipHostFree(h->work_host);
         for (auto &t : h->pending_timers) {
@@ -1903,13 +2361,21 @@ fassmvs_status fassmvs_stage_seed(fassmvs_handle *h, const float *depth_c, const
         a.W[f] = W[f];
         sumG += G[f];
     }
-    for (int j = 0; j < sumG; ++j)
+    std::vector<double> inv(sumG);
+    for (int j = 0; j < sumG; ++j) {
         if (!(fam_delta[j] > 0.0) || !std::isfinite(fam_delta[j])) return fail(h, FASSMVS_EINVAL, "bad plane list");
+        inv[j] = 1.0 / fam_delta[j];
+    }
+    for (int f = 0; f < n_fam; ++f)
+        for (int j = 1; j < G[f]; ++j)
+            if (!(inv[a.goff[f] + j] < inv[a.goff[f] + j - 1]))
+                return fail(h, FASSMVS_EINVAL, "plane lists must increase strictly");
     fassmvs_status st = ensure(h, h->params, (size_t)sumG * 8);
     if (st != FASSMVS_OK) return st;
-    HIPCHK(h, hipMemcpyAsync(h->params.p, fam_delta, (size_t)sumG * 8, hipMemcpyHostToDevice, h->stream),
+    HIPCHK(h, hipMemcpyAsync(h->params.p, inv.data(), (size_t)sumG * 8, hipMemcpyHostToDevice, h->stream),
            "list upload");
-    a.delta = (const double *)h->params.p;
+    HIPCHK(h, hipStreamSynchronize(h->stream), "list upload");
+    a.inv = (const double *)h->params.p;
     a.depth_c = depth_c;
     a.normal_c = normal_c;
     a.dbar = dbar;

@@ -1,11 +1,16 @@
 """Uneven batch: sixteen frames of different resolution (640x480 ..
 1920x1080), view count (2-5, unequal subsets included), plane count
-(64-192, so one or two label pairs per lane) and pyramid depth (2 or 3)
-in flight on the device together, one pipeline handle (own stream) each.
+(64-192, so one or two label pairs per lane) and pyramid depth (2 or 3).
 
-Every frame's maps are identical to the same frame run alone; the coarsest
-level of four of them (5 views in 3 + 2, 192 labels, 2 levels, 2 views)
-matches the oracle at the frame tests' gates."""
+Submitted as one batch on one handle (one sweep launch and one persistent
+aggregation launch per level round, the whole batch replayed from a captured
+graph), every frame's maps are identical to the same frame run alone, on
+the graph's first capture, on its replay and without the graph; the same
+holds with sixteen handles in flight together.  The coarsest level of four
+frames (5 views in 3 + 2, 192 labels, 2 levels, 2 views) matches the oracle
+at the frame tests' gates."""
+import copy
+import os
 import time
 
 import numpy as np
@@ -35,29 +40,38 @@ def _maps(wl):
 
 
 @pytest.fixture(scope="module")
-def runs(fm, frames):
-    """(alone, together, handles kept for level maps) for every frame."""
-    alone = {}
-    t0 = time.perf_counter()
+def alone(fm, frames):
+    """Each frame on a handle of its own (levels kept for the oracle test)."""
+    out, handles = {}, {}
     for sd, wl in frames.items():
-        with fm.Handle(fm.config_from_params(wl["params"])) as h:
-            alone[sd] = h.run_frame(wl)
-    t_alone = time.perf_counter() - t0
-    handles = {sd: fm.Handle(fm.config_from_params(wl["params"], keep_levels=1)) for sd, wl in frames.items()}
-    t0 = time.perf_counter()
-    tickets = {sd: handles[sd].submit_frame(wl["ref"], wl["views"], wl["side"], wl["K"], wl["families"])
-               for sd, wl in frames.items()}
-    together = {}
-    for sd, wl in frames.items():
-        d, n, c = _maps(wl)
-        handles[sd].poll(tickets[sd], d, n, c)
-        together[sd] = dict(depth=d, normal=n, conf=c)
-    t_together = time.perf_counter() - t0
-    print(f"16 uneven frames: one at a time {t_alone * 1e3:.1f} ms (first use of each handle included), "
-          f"all in flight {t_together * 1e3:.1f} ms")
-    yield alone, together, handles
+        h = fm.Handle(fm.config_from_params(wl["params"], keep_levels=1))
+        out[sd] = h.run_frame(wl)
+        handles[sd] = h
+    yield out, handles
     for h in handles.values():
         h.close()
+
+
+@pytest.fixture(scope="module")
+def batched(fm, frames):
+    """The sixteen frames as one batch: graph capture, replay, no graph."""
+    wls = [frames[sd] for sd in scenegen.CONFIG4_SEEDS]
+    res = {}
+    with fm.Handle(fm.config_from_params(wls[0]["params"])) as h:
+        t0 = time.perf_counter()
+        res["first"] = h.run_batch(wls)        # tuning, capture, launch
+        t1 = time.perf_counter()
+        res["replay"] = h.run_batch(wls)
+        t2 = time.perf_counter()
+        res["tuning"] = h.batch_tuning()
+        os.environ["FASSMVS_BATCH_GRAPH"] = "0"
+        try:
+            res["eager"] = h.run_batch(wls)
+        finally:
+            del os.environ["FASSMVS_BATCH_GRAPH"]
+        print(f"batch of 16: first {1e3 * (t1 - t0):.1f} ms (tuning + capture), replay {1e3 * (t2 - t1):.1f} ms, "
+              f"tuning {res['tuning']}")
+    return res
 
 
 def test_shapes_are_uneven(frames):
@@ -73,19 +87,40 @@ def test_shapes_are_uneven(frames):
 
 
 @pytest.mark.parametrize("sd", scenegen.CONFIG4_SEEDS)
-def test_frame_same_alone_and_in_the_batch(runs, sd):
-    alone, together, _ = runs
-    for k in ("depth", "normal", "conf"):
-        assert np.array_equal(alone[sd][k], together[sd][k]), (sd, k)
-    assert np.mean(alone[sd]["depth"] > 0) > 0.5
+def test_frame_same_alone_and_in_the_batch(alone, batched, sd):
+    i = scenegen.CONFIG4_SEEDS.index(sd)
+    for run in ("first", "replay", "eager"):
+        for k in ("depth", "normal", "conf"):
+            assert np.array_equal(alone[0][sd][k], batched[run][i][k]), (sd, run, k)
+    assert np.mean(alone[0][sd]["depth"] > 0) > 0.5
+
+
+def test_batch_tuning_reported(batched):
+    t = batched["tuning"]
+    assert t["rows_per_thread"] in (4, 8) and t["sweep_blocks"] in (4096, 8192, 16384) and t["sweep_ms"] > 0
+
+
+def test_frames_in_flight_on_sixteen_handles(fm, frames, alone):
+    handles = {sd: fm.Handle(fm.config_from_params(wl["params"])) for sd, wl in frames.items()}
+    try:
+        tickets = {sd: handles[sd].submit_frame(wl["ref"], wl["views"], wl["side"], wl["K"], wl["families"])
+                   for sd, wl in frames.items()}
+        for sd, wl in frames.items():
+            d, n, c = _maps(wl)
+            handles[sd].poll(tickets[sd], d, n, c)
+            assert np.array_equal(d, alone[0][sd]["depth"]) and np.array_equal(n, alone[0][sd]["normal"])
+            assert np.array_equal(c, alone[0][sd]["conf"])
+    finally:
+        for h in handles.values():
+            h.close()
 
 
 @pytest.mark.parametrize("sd", ORACLE_SEEDS)
-def test_batch_coarsest_level_matches_oracle(orc, frames, runs, sd):
+def test_batch_coarsest_level_matches_oracle(orc, frames, alone, sd):
     wl = frames[sd]
     top = wl["params"]["n_levels"] - 1
     ref = orc.run_frame(wl, keep=True, levels_only=top)["levels"][top]
-    h = runs[2][sd]
+    h = alone[1][sd]
     lab = h.level_map(top, 4)
     dep = h.level_map(top, 0)
     agree = lab == ref["label"]
@@ -93,3 +128,54 @@ def test_batch_coarsest_level_matches_oracle(orc, frames, runs, sd):
     ok = agree & (ref["depth"] > 0)
     rel = np.abs(dep[ok] - ref["depth"][ok]) / ref["depth"][ok]
     assert np.mean(rel <= 1e-3) >= 0.999, np.max(rel)
+
+
+def test_batch_of_mixed_small_frames_and_fallback_aggregation(fm):
+    """Frames of one batch whose aggregation cannot share the persistent
+    launch (path-gradient SGM) run it frame by frame; a shape change
+    recaptures; each frame equals its run alone."""
+    for variant in (1, 2):
+        wls = []
+        for name in ("config2_small", "config2_ragged", "config3_small"):
+            wl = copy.deepcopy(scenegen.make_workload(name))
+            wl["params"]["sgm_variant"] = variant
+            wls.append(wl)
+        ones = []
+        for wl in wls:
+            with fm.Handle(fm.config_from_params(wl["params"])) as h1:
+                ones.append(h1.run_frame(wl))
+        with fm.Handle(fm.config_from_params(wls[0]["params"])) as h:
+            for order in ([0, 1, 2], [2, 1], [0, 1, 2]):
+                got = h.run_batch([wls[i] for i in order])
+                for i, g in zip(order, got):
+                    for k in ("depth", "normal", "conf"):
+                        assert np.array_equal(g[k], ones[i][k]), (variant, wls[i]["name"], k)
+
+
+def test_batch_errors(fm, frames):
+    wl = frames[scenegen.CONFIG4_SEEDS[0]]
+    with fm.Handle(fm.config_from_params(wl["params"])) as h:
+        with pytest.raises(fm.FassmvsError) as e:
+            h.submit_batch([])
+        assert e.value.status == fm.EINVAL
+        t = h.submit_batch([wl])
+        with pytest.raises(fm.FassmvsError) as e:
+            h.submit_frame(wl["ref"], wl["views"], wl["side"], wl["K"], wl["families"])
+        assert e.value.status == fm.EBUSY
+        with pytest.raises(fm.FassmvsError) as e:
+            h.submit_batch([wl])
+        assert e.value.status == fm.EBUSY
+        d, n, c = _maps(wl)
+        with pytest.raises(fm.FassmvsError) as e:
+            h.poll_batch(t, 1, d)
+        assert e.value.status == fm.EINVAL
+        with pytest.raises(fm.FassmvsError) as e:
+            h.poll_batch(t + 5, 0, d)
+        assert e.value.status == fm.ENOTFOUND
+        assert h.poll_batch(t, 0, d, n, c) == fm.OK
+        ref = h.run_frame(wl)                              # the handle is free again
+        assert np.array_equal(ref["depth"], d)
+        bad = dict(wl, params=dict(wl["params"], n_levels=9))
+        with pytest.raises(fm.FassmvsError) as e:
+            h.submit_batch([wl, bad])
+        assert e.value.status == fm.EINVAL
