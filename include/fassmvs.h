@@ -173,14 +173,18 @@ fassmvs_status fassmvs_poll(fassmvs_handle *h, uint64_t ticket, float *depth, fl
 
 /* ---------------------------------------------------------------------
  * Batched frames: several bundles of uneven size, views, plane count and
- * pyramid height in one submission.  The frames run level round by level
+ * pyramid height in one submission.  The frames are split into groups of
+ * about equal work, each group on a stream of its own forked from and
+ * joined back into the handle's stream.  A group runs level round by level
  * round (every frame's coarsest level first); in each round the sweeps of
- * all frames are one launch and their aggregations one persistent launch
- * over the paths of every frame and direction; the whole batch is captured
- * in a HIP graph once per batch shape and replayed while the shape and the
- * buffers stay; the sweep's tile height and workgroup count are tuned once
- * per shape by timing the candidates (they change no result).  Each frame's
- * maps are those fassmvs_submit_frame gives for the same bundle.
+ * its frames are one launch and their aggregations one persistent launch
+ * per label-pair count over the paths of every frame and direction.  The
+ * whole batch can be captured in a HIP graph once per batch shape and
+ * replayed while the shape and the buffers stay; the sweep's tile height
+ * and workgroup count, the number of groups and the graph are tuned once
+ * per shape by timing the candidates (none of them changes a result).
+ * Each frame's maps are those fassmvs_submit_frame gives for the same
+ * bundle.
  * --------------------------------------------------------------------- */
 #define FASSMVS_MAX_BATCH 64
 
@@ -208,10 +212,13 @@ fassmvs_status fassmvs_submit_batch(fassmvs_handle *h, const fassmvs_frame *fram
 fassmvs_status fassmvs_poll_batch(fassmvs_handle *h, uint64_t ticket, int32_t index, float *depth, float *normal,
                                   float *confidence, int32_t mem_kind, int32_t wait_ms);
 
-/* The sweep configuration the batch tuner chose for the last batch shape:
- * rows per thread (tile height / 4), workgroup target, and the measured
- * sweep time of the batch in ms. */
-fassmvs_status fassmvs_batch_tuning(fassmvs_handle *h, int32_t *rows_per_thread, int32_t *sweep_blocks, double *ms);
+/* What the batch tuner chose for the last batch shape: sweep rows per
+ * thread (tile height / 4), sweep workgroup target, number of frame groups
+ * (each on a stream of its own), whether the batch replays a captured graph
+ * (1) or is launched call by call (0), and the measured time of one batch
+ * in ms.  Any output may be NULL. */
+fassmvs_status fassmvs_batch_tuning(fassmvs_handle *h, int32_t *rows_per_thread, int32_t *sweep_blocks, int32_t *groups,
+                                    int32_t *graph, double *ms);
 
 /* Wait for any frame in flight and release every resource of the handle. */
 void fassmvs_destroy(fassmvs_handle *h);

@@ -81,7 +81,7 @@ def _declare(L):
         "fassmvs_poll": (st, [vp, u64, vp, vp, vp, i32, i32]),
         "fassmvs_submit_batch": (st, [vp, vp, i32, i32, vp]),
         "fassmvs_poll_batch": (st, [vp, u64, i32, vp, vp, vp, i32, i32]),
-        "fassmvs_batch_tuning": (st, [vp, vp, vp, vp]),
+        "fassmvs_batch_tuning": (st, [vp, vp, vp, vp, vp, vp]),
         "fassmvs_destroy": (None, [vp]),
         "fassmvs_last_error": (C.c_char_p, [vp]),
         "fassmvs_stage_times": (st, [vp, vp, vp, i32]),
@@ -462,9 +462,11 @@ class Handle:
         return out
 
     def batch_tuning(self):
-        rpt, blocks, ms = C.c_int32(), C.c_int32(), C.c_double()
-        self._check(lib().fassmvs_batch_tuning(self.h, C.byref(rpt), C.byref(blocks), C.byref(ms)))
-        return dict(rows_per_thread=rpt.value, sweep_blocks=blocks.value, sweep_ms=ms.value)
+        rpt, blocks, groups, graph, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        self._check(lib().fassmvs_batch_tuning(self.h, C.byref(rpt), C.byref(blocks), C.byref(groups), C.byref(graph),
+                                               C.byref(ms)))
+        return dict(rows_per_thread=rpt.value, sweep_blocks=blocks.value, groups=groups.value, graph=bool(graph.value),
+                    batch_ms=ms.value)
 
     def poll(self, ticket, depth=None, normal=None, conf=None, mem_kind=MEM_HOST, wait_ms=-1):
         st = self._check(lib().fassmvs_poll(self.h, ticket, _ptr(depth), _ptr(normal), _ptr(conf),

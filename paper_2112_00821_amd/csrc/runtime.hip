@@ -149,9 +149,13 @@ struct fassmvs_handle {
     };
     std::map<std::string, BatchGraph> graphs;
     struct Tuning {
-        int rpt = 8, target = 8192;
+        int rpt = 8, target = 8192, groups = 1;
+        bool graph = true;
         double ms = 0.0;
     };
+    std::vector<hipStream_t> group_streams;   // one per frame group of a batch
+    std::vector<hipEvent_t> group_ev;         // fork, then one join per group
+    hipEvent_t batch_tev[2] = {nullptr, nullptr};   // tuning timer
     std::map<std::string, Tuning> tuned;
     Tuning last_tuning;
     DevBuf pyr[kMaxViews + 1];       // every level of each image, level 0 first
@@ -1134,29 +1138,48 @@ fassmvs_status copy_out(fassmvs_handle *h, void *dst, const void *src, size_t by
 }
 
 // ---------------------------------------------------------------- batched frames
-// One round of a batch: frame i at its level levels[i] (rounds run from the
-// coarsest level of every frame down, frames with fewer levels finish
-// early), its sweeps in one launch and its aggregations in one persistent
-// launch.
-struct BatchRound {
-    std::vector<int> frames, levels;
-    size_t sweep_off = 0, sgm_off = 0;
-    int sweep_blocks = 0;
-    int sgm_jobs = -1;   // -1: the frames' aggregations run one launch each
-    int kp = 1, nf = 1;
+// A batch runs as G groups of frames, each group on a stream of its own
+// (forked from and joined back into the handle's stream), so the
+// instruction-bound sweeps of one group overlap the memory-bound
+// aggregations of another.  Inside a group, frames run round by round from
+// each frame's coarsest level (frames with fewer levels finish early); a
+// round's sweeps are one launch and its aggregations one persistent launch
+// per label-pair count.
+
+// One persistent aggregation launch over some frames of a round.
+struct SgmLaunch {
+    size_t off = 0;
+    int n = 0, jobs = 0, kp = 1, nf = 1;
     bool win = false, sn = false;
+};
+
+struct BatchRound {
+    std::vector<int> frames, levels;   // frames (batch order) and their level in this round
+    size_t sweep_off = 0;
+    int sweep_blocks = 0;
+    std::vector<SgmLaunch> sgm;
+    std::vector<char> own_sgm;   // per frame of the round: aggregates in launches of its own
+};
+
+struct BatchGroup {
+    std::vector<int> frames;
+    std::vector<BatchRound> rounds;
+    size_t counter_off = 0;   // the persistent aggregation's job counter
+    int rpt = 8;              // sweep rows per thread
 };
 
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxBatchGraphs = 8;   // captured batch graphs kept per handle
+constexpr int kMaxBatchGroups = 8;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // The batch's shape: sizes, view split, plane counts and windows of every
 // frame and level.  With values, also what the per-frame launches take by
 // value (intrinsics, plane normals, list steps, penalties), so that a
 // captured graph is replayed only for frames that agree in all of it.
-std::string batch_signature(fassmvs_handle *h, int n, int rpt, int target, bool values) {
-    std::string sig = std::to_string(rpt) + "/" + std::to_string(target);
+std::string batch_signature(fassmvs_handle *h, int n, const fassmvs_handle::Tuning *t, bool values) {
+    std::string sig = t ? std::to_string(t->rpt) + "/" + std::to_string(t->target) + "/" + std::to_string(t->groups)
+                        : std::string("shape");
     auto raw = [&sig](const void *p, size_t b) { sig.append((const char *)p, b); };
     for (int i = 0; i < n; ++i) {
         const FramePlan &P = h->children[i]->plan;
@@ -1182,29 +1205,77 @@ std::string batch_signature(fassmvs_handle *h, int n, int rpt, int target, bool 
     return sig;
 }
 
-// Every round's argument blocks into the pinned stage (grown as needed);
-// *bytes receives their size, the counter of the persistent aggregation
-// sitting at its end.
-fassmvs_status batch_prepare(fassmvs_handle *h, int n, int rpt, int target, std::vector<BatchRound> &rounds,
-                             size_t *bytes) {
-    int R = 0;
-    for (int i = 0; i < n; ++i) R = std::max(R, h->children[i]->plan.n_levels);
-    rounds.assign(R, BatchRound());
-    size_t off = 0;
-    for (int r = 0; r < R; ++r) {
-        BatchRound &br = rounds[r];
-        for (int i = 0; i < n; ++i) {
-            const int l = h->children[i]->plan.n_levels - 1 - r;
-            if (l < 0) continue;
-            br.frames.push_back(i);
-            br.levels.push_back(l);
-        }
-        br.sweep_off = off;
-        off = align_up(off + sweep_batch_bytes((int)br.frames.size()));
-        br.sgm_off = off;
-        off = align_up(off + sgm_batch_bytes((int)br.frames.size()));
+// Frames into groups of about equal work (pixels x labels x views over the
+// levels), largest first.
+std::vector<std::vector<int>> batch_groups(fassmvs_handle *h, int n, int G) {
+    std::vector<std::pair<double, int>> work(n);
+    for (int i = 0; i < n; ++i) {
+        const FramePlan &P = h->children[i]->plan;
+        double w = 0.0;
+        for (int l = 0; l < P.n_levels; ++l) w += (double)P.lv[l].w * P.lv[l].h * P.lv[l].D * P.n_views;
+        work[i] = {w, i};
     }
-    const size_t total = off + kAlign;
+    std::stable_sort(work.begin(), work.end(), [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+        return x.first > y.first;
+    });
+    G = std::max(1, std::min(G, n));
+    std::vector<std::vector<int>> groups(G);
+    std::vector<double> load(G, 0.0);
+    for (auto &wi : work) {
+        const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        groups[g].push_back(wi.second);
+        load[g] += wi.first;
+    }
+    for (auto &g : groups) std::sort(g.begin(), g.end());
+    return groups;
+}
+
+// Every group's and round's argument blocks into the pinned stage (grown as
+// needed); *bytes receives their size, the groups' job counters at its end.
+fassmvs_status batch_prepare(fassmvs_handle *h, int n, const fassmvs_handle::Tuning &t,
+                             std::vector<BatchGroup> &groups, size_t *bytes) {
+    const auto assign = batch_groups(h, n, t.groups);
+    groups.assign(assign.size(), BatchGroup());
+    // the rounds and their frames; label-pair classes decide the layout
+    size_t off = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        BatchGroup &g = groups[gi];
+        g.frames = assign[gi];
+        g.rpt = t.rpt;
+        int R = 0;
+        for (int i : g.frames) R = std::max(R, h->children[i]->plan.n_levels);
+        g.rounds.assign(R, BatchRound());
+        for (int r = 0; r < R; ++r) {
+            BatchRound &br = g.rounds[r];
+            for (int i : g.frames) {
+                const int l = h->children[i]->plan.n_levels - 1 - r;
+                if (l < 0) continue;
+                br.frames.push_back(i);
+                br.levels.push_back(l);
+            }
+            br.sweep_off = off;
+            off = align_up(off + sweep_batch_bytes((int)br.frames.size()));
+            int count[5] = {0, 0, 0, 0, 0};
+            for (size_t j = 0; j < br.frames.size(); ++j) {
+                const int D = h->children[br.frames[j]]->plan.lv[br.levels[j]].D;
+                count[std::min(4, (D + 127) / 128)]++;
+            }
+            for (int kp = 1; kp <= 4; ++kp) {
+                if (!count[kp]) continue;
+                SgmLaunch L;
+                L.off = off;
+                L.kp = kp;
+                L.n = count[kp];
+                br.sgm.push_back(L);
+                off = align_up(off + sgm_batch_bytes(count[kp]));
+            }
+        }
+    }
+    for (auto &g : groups) {
+        g.counter_off = off;
+        off += kAlign;
+    }
+    const size_t total = off;
     if (h->batch_stage_bytes < total) {
         if (h->batch_stage) hipHostFree(h->batch_stage);
         h->batch_stage = nullptr;
@@ -1216,61 +1287,70 @@ fassmvs_status batch_prepare(fassmvs_handle *h, int n, int rpt, int target, std:
         }
         h->batch_stage_bytes = total;
     }
-    for (auto &br : rounds) {
-        const int m = (int)br.frames.size();
-        std::vector<SweepArgs> sw(m);
-        std::vector<SgmArgs> sg(m);
-        for (int j = 0; j < m; ++j) {
-            fassmvs_handle *c = h->children[br.frames[j]];
-            sw[j] = sweep_args(c, c->plan, br.levels[j]);
-            sg[j] = sgm_args(c, c->plan, br.levels[j]);
+    uint8_t *stage = (uint8_t *)h->batch_stage;
+    // the path-gradient form and the debug sums aggregate frame by frame
+    const bool shared_sgm = !h->cfg.sgm_debug && h->cfg.sgm_variant != 2;
+    for (auto &g : groups)
+        for (auto &br : g.rounds) {
+            const int m = (int)br.frames.size();
+            std::vector<SweepArgs> sw(m);
+            for (int j = 0; j < m; ++j) {
+                fassmvs_handle *c = h->children[br.frames[j]];
+                sw[j] = sweep_args(c, c->plan, br.levels[j]);
+            }
+            br.sweep_blocks = prepare_sweep_batch(sw.data(), m, t.rpt, t.target, stage + br.sweep_off);
+            if (br.sweep_blocks < 0) return fail(h, FASSMVS_EINVAL, "frames of a batch must share the matching cost");
+            br.own_sgm.assign(m, shared_sgm ? 0 : 1);
+            for (auto &L : br.sgm) {
+                std::vector<SgmArgs> sg;
+                std::vector<int> idx;
+                for (int j = 0; j < m; ++j) {
+                    fassmvs_handle *c = h->children[br.frames[j]];
+                    const int D = c->plan.lv[br.levels[j]].D;
+                    if (std::min(4, (D + 127) / 128) != L.kp) continue;
+                    sg.push_back(sgm_args(c, c->plan, br.levels[j]));
+                    idx.push_back(j);
+                }
+                L.jobs = shared_sgm ? prepare_sgm_batch(sg.data(), (int)sg.size(), stage + L.off, &L.kp, &L.win, &L.sn,
+                                                        &L.nf)
+                                    : -1;
+                if (L.jobs < 0)
+                    for (int j : idx) br.own_sgm[j] = 1;
+            }
         }
-        br.sweep_blocks = prepare_sweep_batch(sw.data(), m, rpt, target, (uint8_t *)h->batch_stage + br.sweep_off);
-        if (br.sweep_blocks < 0) return fail(h, FASSMVS_EINVAL, "frames of a batch must share the matching cost");
-        // the path-gradient form and the debug sums run frame by frame
-        br.sgm_jobs = (h->cfg.sgm_debug || h->cfg.sgm_variant == 2)
-                          ? -1
-                          : prepare_sgm_batch(sg.data(), m, (uint8_t *)h->batch_stage + br.sgm_off, &br.kp,
-                                              &br.win, &br.sn, &br.nf);
-    }
     *bytes = total;
     return FASSMVS_OK;
 }
 
-// The batch's launches, all on the handle's stream (kernels only, so the
-// sequence can be captured in a graph).  With ev (two events per round) the
-// sweeps are timed.
-fassmvs_status batch_enqueue(fassmvs_handle *h, int n, const std::vector<BatchRound> &rounds, int rpt,
-                             size_t counter_off, hipEvent_t *ev) {
+// One group's launches on stream s (kernels only, so the sequence can be
+// captured in a graph).
+fassmvs_status batch_enqueue_group(fassmvs_handle *h, const BatchGroup &g, hipStream_t s) {
     const fassmvs_config &c = h->cfg;
     fassmvs_status st;
-    for (int i = 0; i < n; ++i)
+    for (int i : g.frames) {
+        h->children[i]->stream = s;
         if ((st = enqueue_pyramid(h->children[i], h->children[i]->plan)) != FASSMVS_OK) return st;
+    }
     uint8_t *dev = (uint8_t *)h->batch_dev.p;
-    unsigned *counter = (unsigned *)(dev + counter_off);
-    for (size_t r = 0; r < rounds.size(); ++r) {
-        const BatchRound &br = rounds[r];
+    unsigned *counter = (unsigned *)(dev + g.counter_off);
+    for (const BatchRound &br : g.rounds) {
         const int m = (int)br.frames.size();
         for (int j = 0; j < m; ++j) {
             fassmvs_handle *ch = h->children[br.frames[j]];
             if ((st = enqueue_census(ch, ch->plan, br.levels[j])) != FASSMVS_OK) return fail(h, st, ch->err);
         }
-        if (ev) HIPCHK(h, hipEventRecord(ev[2 * r], h->stream), "timing event");
-        HIPCHK(h, launch_sweep_batch(dev + br.sweep_off, m, br.sweep_blocks, rpt, c.census_w, c.census_h, c.cost,
-                                     h->stream),
+        HIPCHK(h, launch_sweep_batch(dev + br.sweep_off, m, br.sweep_blocks, g.rpt, c.census_w, c.census_h, c.cost, s),
                "batched sweep launch");
-        if (ev) HIPCHK(h, hipEventRecord(ev[2 * r + 1], h->stream), "timing event");
-        if (br.sgm_jobs >= 0) {
-            HIPCHK(h, launch_sgm_batch(dev + br.sgm_off, m, br.sgm_jobs, br.kp, br.win, br.sn, br.nf, counter,
-                                       h->stream),
-                   "batched aggregation launch");
-        }
+        for (const SgmLaunch &L : br.sgm)
+            if (L.jobs >= 0)
+                HIPCHK(h, launch_sgm_batch(dev + L.off, L.n, L.jobs, L.kp, L.win, L.sn, L.nf, counter, s),
+                       "batched aggregation launch");
         for (int j = 0; j < m; ++j) {
             fassmvs_handle *ch = h->children[br.frames[j]];
             const FramePlan &P = ch->plan;
             const int l = br.levels[j];
             const SgmArgs sa = sgm_args(ch, P, l);
-            if (br.sgm_jobs < 0) {
+            if (br.own_sgm[j]) {
                 uint16_t *bufs[8];
                 for (int i = 0; i < 8; ++i) bufs[i] = (uint16_t *)ch->sgmbuf[i].p;
                 PgGeom pgg{(const double *)ch->params.p + P.lv[l].d_off, P.fam_n};
@@ -1287,12 +1367,49 @@ fassmvs_status batch_enqueue(fassmvs_handle *h, int n, const std::vector<BatchRo
     return FASSMVS_OK;
 }
 
+// The whole batch on the handle's stream: groups forked onto their own
+// streams and joined back.  With ev, ev[0] / ev[1] bracket it.
+fassmvs_status batch_enqueue(fassmvs_handle *h, const std::vector<BatchGroup> &groups, hipEvent_t *ev) {
+    fassmvs_status st;
+    if (ev) HIPCHK(h, hipEventRecord(ev[0], h->stream), "timing event");
+    if (groups.size() == 1) {
+        if ((st = batch_enqueue_group(h, groups[0], h->stream)) != FASSMVS_OK) return st;
+    } else {
+        HIPCHK(h, hipEventRecord(h->group_ev[0], h->stream), "batch fork");
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            HIPCHK(h, hipStreamWaitEvent(h->group_streams[gi], h->group_ev[0], 0), "batch fork");
+            if ((st = batch_enqueue_group(h, groups[gi], h->group_streams[gi])) != FASSMVS_OK) return st;
+            HIPCHK(h, hipEventRecord(h->group_ev[gi + 1], h->group_streams[gi]), "batch join");
+            HIPCHK(h, hipStreamWaitEvent(h->stream, h->group_ev[gi + 1], 0), "batch join");
+        }
+    }
+    if (ev) HIPCHK(h, hipEventRecord(ev[1], h->stream), "timing event");
+    return FASSMVS_OK;
+}
+
 fassmvs_status batch_upload_args(fassmvs_handle *h, size_t bytes) {
     if (h->batch_dev.bytes < bytes) {
         fassmvs_status st = ensure(h, h->batch_dev, bytes);
         if (st != FASSMVS_OK) return st;
     }
     HIPCHK(h, hipMemcpyAsync(h->batch_dev.p, h->batch_stage, bytes, hipMemcpyHostToDevice, h->stream), "batch args");
+    return FASSMVS_OK;
+}
+
+// Streams and fork / join events for up to kMaxBatchGroups groups.
+fassmvs_status batch_streams(fassmvs_handle *h) {
+    while ((int)h->group_streams.size() < kMaxBatchGroups) {
+        hipStream_t s;
+        HIPCHK(h, hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "batch stream");
+        h->group_streams.push_back(s);
+    }
+    while ((int)h->group_ev.size() < kMaxBatchGroups + 1) {
+        hipEvent_t e;
+        HIPCHK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "batch event");
+        h->group_ev.push_back(e);
+    }
+    for (auto &e : h->batch_tev)
+        if (!e) HIPCHK(h, hipEventCreate(&e), "timing event");
     return FASSMVS_OK;
 }
 
@@ -1521,86 +1638,120 @@ fassmvs_status fassmvs_submit_batch(fassmvs_handle *h, const fassmvs_frame *fram
         if (st != FASSMVS_OK) return fail(h, st, "frame " + std::to_string(i) + ": " + ch->err);
         if ((st = alloc_frame(ch, ch->plan)) != FASSMVS_OK) return fail(h, st, "frame " + std::to_string(i) + ": " + ch->err);
     }
-    const bool use_graph = !env_off("FASSMVS_BATCH_GRAPH"), tune = !env_off("FASSMVS_BATCH_TUNE");
-    // the sweep's tile height and workgroup target: tuned once per batch shape
-    // (neither changes a result)
-    std::string shape = batch_signature(h, n_frames, 0, 0, false);
-    auto tit = h->tuned.find(shape);
+    const bool graph_on = !env_off("FASSMVS_BATCH_GRAPH"), tune = !env_off("FASSMVS_BATCH_TUNE");
     fassmvs_status st;
+    if ((st = batch_streams(h)) != FASSMVS_OK) return st;
     for (int i = 0; i < n_frames; ++i) {
         const fassmvs_frame &fr = frames[i];
-        if ((st = upload_frame(h->children[i], h->children[i]->plan, fr.ref, fr.views, mem_kind)) != FASSMVS_OK)
-            return fail(h, st, h->children[i]->err);
+        fassmvs_handle *ch = h->children[i];
+        ch->stream = h->stream;
+        if ((st = upload_frame(ch, ch->plan, fr.ref, fr.views, mem_kind)) != FASSMVS_OK) return fail(h, st, ch->err);
     }
-    std::vector<BatchRound> rounds;
-    size_t bytes = 0;
-    if (tit == h->tuned.end() && tune) {
-        // time the batch once per candidate (the sweeps, HIP events), keep the fastest
-        static const int kRpt[] = {8, 4};
-        static const int kTarget[] = {4096, 8192, 16384};
+    // One run of the batch with tuning t, from a captured graph or launch by
+    // launch; with ms, timed (HIP events on the handle's stream).
+    auto run = [&](const fassmvs_handle::Tuning &t, bool graph, double *ms) -> fassmvs_status {
+        std::vector<BatchGroup> groups;
+        size_t bytes = 0;
+        fassmvs_status s2;
+        if ((s2 = batch_prepare(h, n_frames, t, groups, &bytes)) != FASSMVS_OK) return s2;
+        if ((s2 = batch_upload_args(h, bytes)) != FASSMVS_OK) return s2;
+        hipEvent_t *ev = ms ? h->batch_tev : nullptr;
+        if (graph) {
+            uint64_t gen = h->gen;
+            for (int i = 0; i < n_frames; ++i) gen += h->children[i]->gen;
+            const std::string key = batch_signature(h, n_frames, &t, true);
+            if (h->graphs.size() >= kMaxBatchGraphs && !h->graphs.count(key)) {
+                for (auto &kv : h->graphs)
+                    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+                h->graphs.clear();
+            }
+            auto &g = h->graphs[key];
+            if (!g.exec || g.gen != gen) {
+                if (g.exec) hipGraphExecDestroy(g.exec);
+                g.exec = nullptr;
+                // the launches of the whole batch, captured once and replayed
+                // while the shape and the buffers stay
+                HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed), "graph capture");
+                s2 = batch_enqueue(h, groups, nullptr);
+                hipGraph_t graph_ = nullptr;
+                hipError_t e = hipStreamEndCapture(h->stream, &graph_);
+                if (s2 != FASSMVS_OK) {
+                    if (graph_) hipGraphDestroy(graph_);
+                    h->graphs.erase(key);
+                    return s2;
+                }
+                HIPCHK(h, e, "graph capture");
+                e = hipGraphInstantiate(&g.exec, graph_, nullptr, nullptr, 0);
+                hipGraphDestroy(graph_);
+                HIPCHK(h, e, "graph instantiation");
+                g.gen = gen;
+            }
+            if (ev) HIPCHK(h, hipEventRecord(ev[0], h->stream), "timing event");
+            HIPCHK(h, hipGraphLaunch(g.exec, h->stream), "graph launch");
+            if (ev) HIPCHK(h, hipEventRecord(ev[1], h->stream), "timing event");
+        } else if ((s2 = batch_enqueue(h, groups, ev)) != FASSMVS_OK) {
+            return s2;
+        }
+        if (ms) {
+            HIPCHK(h, hipEventSynchronize(ev[1]), "batch tuning run");
+            float t_ = 0.0f;
+            HIPCHK(h, hipEventElapsedTime(&t_, ev[0], ev[1]), "timing");
+            *ms = t_;
+        }
+        return FASSMVS_OK;
+    };
+    // The sweep's tile height and workgroup target, the number of frame
+    // groups and the graph: tuned once per batch shape by timing whole runs
+    // (none of them changes a result).
+    const std::string shape = batch_signature(h, n_frames, nullptr, false);
+    auto tit = h->tuned.find(shape);
+    fassmvs_handle::Tuning t;
+    {
+        // untuned: FASSMVS_BATCH_GROUPS groups (default 2)
+        const char *e = std::getenv("FASSMVS_BATCH_GROUPS");
+        const int G = e && std::atoi(e) > 0 ? std::atoi(e) : 2;
+        t.groups = std::max(1, std::min({G, n_frames, kMaxBatchGroups}));
+    }
+    t.graph = graph_on;
+    if (tit != h->tuned.end()) {
+        t = tit->second;
+    } else if (tune) {
+        // the group count at the default sweep shape, then the sweep shape
+        // at that count; graphs timed on their first replay
         fassmvs_handle::Tuning best;
         best.ms = 1e30;
-        std::vector<hipEvent_t> ev;
-        for (int rpt : kRpt)
-            for (int target : kTarget) {
-                if ((st = batch_prepare(h, n_frames, rpt, target, rounds, &bytes)) != FASSMVS_OK) return st;
-                if ((st = batch_upload_args(h, bytes)) != FASSMVS_OK) return st;
-                while (ev.size() < 2 * rounds.size()) {
-                    hipEvent_t e;
-                    HIPCHK(h, hipEventCreate(&e), "timing event");
-                    ev.push_back(e);
-                }
-                if ((st = batch_enqueue(h, n_frames, rounds, rpt, bytes - kAlign, ev.data())) != FASSMVS_OK) return st;
-                HIPCHK(h, hipStreamSynchronize(h->stream), "batch tuning run");
-                double ms = 0.0;
-                for (size_t r = 0; r < rounds.size(); ++r) {
-                    float t = 0.0f;
-                    HIPCHK(h, hipEventElapsedTime(&t, ev[2 * r], ev[2 * r + 1]), "timing");
-                    ms += t;
-                }
-                if (ms < best.ms) best = fassmvs_handle::Tuning{rpt, target, ms};
+        auto trial = [&](int rpt, int target, int G) -> fassmvs_status {
+            fassmvs_handle::Tuning c;
+            c.rpt = rpt;
+            c.target = target;
+            c.groups = G;
+            c.graph = graph_on;
+            fassmvs_status s2 = FASSMVS_OK;
+            if (graph_on) s2 = run(c, true, nullptr);
+            if (s2 == FASSMVS_OK) s2 = run(c, graph_on, &c.ms);
+            if (s2 == FASSMVS_OK && c.ms < best.ms) best = c;
+            return s2;
+        };
+        for (int G = 1; G <= std::min(n_frames, kMaxBatchGroups); G *= 2)
+            if ((st = trial(8, 8192, G)) != FASSMVS_OK) return st;
+        const int G = best.groups;
+        for (int rpt : {8, 4})
+            for (int target : {8192, 16384})
+                if (!(rpt == 8 && target == 8192) && (st = trial(rpt, target, G)) != FASSMVS_OK) return st;
+        if (graph_on) {
+            // launched call by call instead, if that is faster
+            double e = 0.0;
+            if ((st = run(best, false, &e)) != FASSMVS_OK) return st;
+            if (e < best.ms) {
+                best.graph = false;
+                best.ms = e;
             }
-        for (auto e : ev) hipEventDestroy(e);
-        tit = h->tuned.emplace(shape, fassmvs_handle::Tuning{best.rpt, best.target, best.ms}).first;
-    }
-    const int rpt = tit != h->tuned.end() ? tit->second.rpt : 8;
-    const int target = tit != h->tuned.end() ? tit->second.target : 8192;
-    if (tit != h->tuned.end()) h->last_tuning = tit->second;
-    if ((st = batch_prepare(h, n_frames, rpt, target, rounds, &bytes)) != FASSMVS_OK) return st;
-    if ((st = batch_upload_args(h, bytes)) != FASSMVS_OK) return st;
-    if (use_graph) {
-        uint64_t gen = h->gen;
-        for (int i = 0; i < n_frames; ++i) gen += h->children[i]->gen;
-        const std::string key = batch_signature(h, n_frames, rpt, target, true);
-        if (h->graphs.size() >= kMaxBatchGraphs && !h->graphs.count(key)) {
-            for (auto &kv : h->graphs)
-                if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-            h->graphs.clear();
         }
-        auto &g = h->graphs[key];
-        if (!g.exec || g.gen != gen) {
-            if (g.exec) hipGraphExecDestroy(g.exec);
-            g.exec = nullptr;
-            // the launches of the whole batch, captured once and replayed while
-            // the shape and the buffers stay
-            HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed), "graph capture");
-            st = batch_enqueue(h, n_frames, rounds, rpt, bytes - kAlign, nullptr);
-            hipGraph_t graph = nullptr;
-            hipError_t e = hipStreamEndCapture(h->stream, &graph);
-            if (st != FASSMVS_OK) {
-                if (graph) hipGraphDestroy(graph);
-                return st;
-            }
-            HIPCHK(h, e, "graph capture");
-            e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-            hipGraphDestroy(graph);
-            HIPCHK(h, e, "graph instantiation");
-            g.gen = gen;
-        }
-        HIPCHK(h, hipGraphLaunch(g.exec, h->stream), "graph launch");
-    } else if ((st = batch_enqueue(h, n_frames, rounds, rpt, bytes - kAlign, nullptr)) != FASSMVS_OK) {
-        return st;
+        t = best;
+        h->tuned[shape] = t;
     }
+    h->last_tuning = t;
+    if ((st = run(t, t.graph && graph_on, nullptr)) != FASSMVS_OK) return st;
     HIPCHK(h, hipEventRecord(h->done, h->stream), "event record");
     h->batch_n = n_frames;
     h->batch_busy = true;
@@ -1646,11 +1797,14 @@ fassmvs_status fassmvs_poll_batch(fassmvs_handle *h, uint64_t ticket, int32_t in
     return FASSMVS_OK;
 }
 
-fassmvs_status fassmvs_batch_tuning(fassmvs_handle *h, int32_t *rows_per_thread, int32_t *sweep_blocks, double *ms) {
+fassmvs_status fassmvs_batch_tuning(fassmvs_handle *h, int32_t *rows_per_thread, int32_t *sweep_blocks,
+                                    int32_t *groups, int32_t *graph, double *ms) {
     if (!h) return FASSMVS_EINVAL;
     std::lock_guard<std::mutex> lk(h->mu);
     if (rows_per_thread) *rows_per_thread = h->last_tuning.rpt;
     if (sweep_blocks) *sweep_blocks = h->last_tuning.target;
+    if (groups) *groups = h->last_tuning.groups;
+    if (graph) *graph = h->last_tuning.graph ? 1 : 0;
     if (ms) *ms = h->last_tuning.ms;
     return FASSMVS_OK;
 }
@@ -1772,9 +1926,13 @@ void fassmvs_destroy(fassmvs_handle *h) {
         std::lock_guard<std::mutex> lk(h->mu);
         hipSetDevice(h->cfg.device);
         hipStreamSynchronize(h->stream);
-        // batch slots share this stream: released before it
+        // batch slots run on this stream and the group streams: released before them
         for (auto *c : h->children) fassmvs_destroy(c);
         h->children.clear();
+        for (auto s_ : h->group_streams) hipStreamDestroy(s_);
+        for (auto e : h->group_ev) hipEventDestroy(e);
+        for (auto e : h->batch_tev)
+            if (e) hipEventDestroy(e);
         for (auto &b : h->pyr) release(b);
         release(h->ct);
         release(h->S);

@@ -69,8 +69,18 @@ def batched(fm, frames):
             res["eager"] = h.run_batch(wls)
         finally:
             del os.environ["FASSMVS_BATCH_GRAPH"]
-        print(f"batch of 16: first {1e3 * (t1 - t0):.1f} ms (tuning + capture), replay {1e3 * (t2 - t1):.1f} ms, "
-              f"tuning {res['tuning']}")
+    # untuned, with one and with four frame groups
+    for G, graph in ((1, "1"), (4, "1"), (4, "0")):
+        os.environ.update(FASSMVS_BATCH_TUNE="0", FASSMVS_BATCH_GROUPS=str(G), FASSMVS_BATCH_GRAPH=graph)
+        try:
+            with fm.Handle(fm.config_from_params(wls[0]["params"])) as h:
+                res[f"groups{G}_graph{graph}"] = h.run_batch(wls)
+                assert h.batch_tuning()["groups"] == G
+        finally:
+            for k in ("FASSMVS_BATCH_TUNE", "FASSMVS_BATCH_GROUPS", "FASSMVS_BATCH_GRAPH"):
+                del os.environ[k]
+    print(f"batch of 16: first {1e3 * (t1 - t0):.1f} ms (tuning + capture), replay {1e3 * (t2 - t1):.1f} ms, "
+          f"tuning {res['tuning']}")
     return res
 
 
@@ -89,7 +99,7 @@ def test_shapes_are_uneven(frames):
 @pytest.mark.parametrize("sd", scenegen.CONFIG4_SEEDS)
 def test_frame_same_alone_and_in_the_batch(alone, batched, sd):
     i = scenegen.CONFIG4_SEEDS.index(sd)
-    for run in ("first", "replay", "eager"):
+    for run in ("first", "replay", "eager", "groups1_graph1", "groups4_graph1", "groups4_graph0"):
         for k in ("depth", "normal", "conf"):
             assert np.array_equal(alone[0][sd][k], batched[run][i][k]), (sd, run, k)
     assert np.mean(alone[0][sd]["depth"] > 0) > 0.5
@@ -97,7 +107,8 @@ def test_frame_same_alone_and_in_the_batch(alone, batched, sd):
 
 def test_batch_tuning_reported(batched):
     t = batched["tuning"]
-    assert t["rows_per_thread"] in (4, 8) and t["sweep_blocks"] in (4096, 8192, 16384) and t["sweep_ms"] > 0
+    assert t["rows_per_thread"] in (4, 8) and t["sweep_blocks"] in (8192, 16384) and t["groups"] in (1, 2, 4, 8)
+    assert t["batch_ms"] > 0
 
 
 def test_frames_in_flight_on_sixteen_handles(fm, frames, alone):
