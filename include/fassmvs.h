@@ -234,11 +234,31 @@ fassmvs_status fassmvs_stage_times(fassmvs_handle *h, double *ms, int32_t *count
 fassmvs_status fassmvs_reset_stage_times(fassmvs_handle *h);
 const char *fassmvs_stage_name(int32_t stage);
 
+/* The same per-stage times for the steps of one pyramid level (0 = full
+ * resolution); frame-wide steps (upload, pyramid, output) belong to no
+ * level. */
+fassmvs_status fassmvs_stage_times_level(fassmvs_handle *h, int32_t level, double *ms, int32_t *counts, int32_t n);
+
+/* One timed step of a frame: stage id, pyramid level (-1: frame-wide),
+ * start on the stream relative to the frame's submission, and duration. */
+typedef struct {
+    int32_t stage;
+    int32_t level;
+    double start_ms;
+    double ms;
+} fassmvs_timeline_entry;
+
+/* The timeline of the last polled frame (cfg.profile = 1), in enqueue
+ * order: up to max_entries entries into out, *n_entries the full count. */
+fassmvs_status fassmvs_frame_timeline(fassmvs_handle *h, fassmvs_timeline_entry *out, int32_t max_entries,
+                                      int32_t *n_entries);
+
 /* Work units of the last frame, for throughput and roofline figures:
  * out[0] = sum over levels of pixels x labels (pixel-hypotheses),
  * out[1] = pixel-hypotheses x matching views, out[2] = labels actually
  * evaluated by the sweep (pixel-hypotheses including tile-union work),
- * out[3] = bytes the SGM stage moves by design. */
+ * out[3] = bytes the SGM stage moves by design, out[4 + l] = pixels x
+ * labels of level l (0 for levels the frame does not have; n up to 9). */
 fassmvs_status fassmvs_frame_work(fassmvs_handle *h, double *out, int32_t n);
 
 /* Copy a per-level map of the last completed frame (cfg.keep_levels = 1)

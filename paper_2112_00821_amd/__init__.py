@@ -87,6 +87,8 @@ def _declare(L):
         "fassmvs_stage_times": (st, [vp, vp, vp, i32]),
         "fassmvs_reset_stage_times": (st, [vp]),
         "fassmvs_stage_name": (C.c_char_p, [i32]),
+        "fassmvs_stage_times_level": (st, [vp, i32, vp, vp, i32]),
+        "fassmvs_frame_timeline": (st, [vp, vp, i32, vp]),
         "fassmvs_frame_work": (st, [vp, vp, i32]),
         "fassmvs_level_map": (st, [vp, i32, i32, vp, sz]),
         "fassmvs_device_alloc": (st, [vp, sz, vp]),
@@ -213,6 +215,10 @@ def _families(families):
             fams[i].count = int(f["count"])
     fams._lists = keep
     return fams
+
+
+class TimelineEntry(C.Structure):
+    _fields_ = [("stage", C.c_int32), ("level", C.c_int32), ("start_ms", C.c_double), ("ms", C.c_double)]
 
 
 class Frame(C.Structure):
@@ -489,13 +495,28 @@ class Handle:
         self._check(lib().fassmvs_stage_times(self.h, ms, n, N_STAGES))
         return {lib().fassmvs_stage_name(i).decode(): (ms[i], n[i]) for i in range(N_STAGES)}
 
+    def stage_times_level(self, level):
+        ms = (C.c_double * N_STAGES)()
+        n = (C.c_int32 * N_STAGES)()
+        self._check(lib().fassmvs_stage_times_level(self.h, level, ms, n, N_STAGES))
+        return {lib().fassmvs_stage_name(i).decode(): (ms[i], n[i]) for i in range(N_STAGES)}
+
+    def frame_timeline(self):
+        """The last polled frame's timed steps: (stage, level, start_ms, ms)."""
+        n = C.c_int32()
+        self._check(lib().fassmvs_frame_timeline(self.h, None, 0, C.byref(n)))
+        buf = (TimelineEntry * max(1, n.value))()
+        self._check(lib().fassmvs_frame_timeline(self.h, buf, n.value, C.byref(n)))
+        return [(lib().fassmvs_stage_name(e.stage).decode(), e.level, e.start_ms, e.ms) for e in buf[:n.value]]
+
     def reset_stage_times(self):
         self._check(lib().fassmvs_reset_stage_times(self.h))
 
     def frame_work(self):
-        out = (C.c_double * 4)()
-        self._check(lib().fassmvs_frame_work(self.h, out, 4))
-        return dict(pixel_hyp=out[0], pixel_hyp_views=out[1], sweep_evaluated=out[2], sgm_design_bytes=out[3])
+        out = (C.c_double * 9)()
+        self._check(lib().fassmvs_frame_work(self.h, out, 9))
+        return dict(pixel_hyp=out[0], pixel_hyp_views=out[1], sweep_evaluated=out[2], sgm_design_bytes=out[3],
+                    pixel_hyp_level=[out[4 + l] for l in range(5)])
 
     def level_size(self, level):
         buf = (C.c_int32 * 2)()

@@ -1,6 +1,8 @@
 // Handle internals the served form uses to admit frames against the device
 // memory its slots actually hold (not part of the public C ABI).
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include "../../include/fassmvs.h"
 
 namespace fmvs {
@@ -15,4 +17,16 @@ fassmvs_status handle_growth(fassmvs_handle *h, const fassmvs_image *ref, const 
                              const fassmvs_plane_family *families, int32_t n_families, uint64_t *grow);
 // Free every device buffer of a handle with no frame in flight.
 void handle_trim(fassmvs_handle *h);
+// Bytes of an image's whole pyramid (levels halved with integer division,
+// level 0 first, each level's rows packed) for n_levels levels.
+size_t pyramid_bytes(int w, int h, int n_levels);
+// Enqueue the pyramid levels 1..n_levels-1 of the level-0 image at img (the
+// layout above) on stream s.
+hipError_t pyramid_build(uint8_t *img, int w, int h, int n_levels, hipStream_t s);
+// fassmvs_submit_frame with device images that already carry their whole
+// pyramid (the layout above, stride = width): the pipeline copies the
+// levels instead of rebuilding them.
+fassmvs_status handle_submit_pyramids(fassmvs_handle *h, const fassmvs_image *ref, const fassmvs_image *views,
+                                      const int8_t *view_side, int32_t n_views, const double K[9],
+                                      const fassmvs_plane_family *families, int32_t n_families, uint64_t *ticket);
 }  // namespace fmvs

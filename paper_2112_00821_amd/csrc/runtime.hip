@@ -108,7 +108,7 @@ struct FramePlan {
 };
 
 struct TimedEvent {
-    int stage;
+    int stage, level;
     hipEvent_t a, b;
 };
 
@@ -175,6 +175,12 @@ struct fassmvs_handle {
     std::vector<hipEvent_t> event_pool;
     double stage_ms[ST_COUNT] = {};
     int32_t stage_n[ST_COUNT] = {};
+    double stage_ms_lv[FASSMVS_MAX_LEVELS][ST_COUNT] = {};
+    int32_t stage_n_lv[FASSMVS_MAX_LEVELS][ST_COUNT] = {};
+    int cur_level = -1;                 // level the timers being enqueued belong to (-1: frame-wide)
+    bool prebuilt = false;              // this frame's device images carry their whole pyramids
+    hipEvent_t frame_t0 = nullptr;      // the frame's start on the stream (profiling)
+    std::vector<fassmvs_timeline_entry> timeline;   // the last polled frame's timed steps
     double last_work[4] = {};
     unsigned long long sweep_work = 0;
     unsigned long long *work_host = nullptr;   // pinned: the counter's copy must not block the submit
@@ -260,7 +266,7 @@ struct Timer {
             hipEvent_t b = get_event(h);
             if (b) {
                 hipEventRecord(b, h->stream);
-                h->pending_timers.push_back({stage, a, b});
+                h->pending_timers.push_back({stage, h->cur_level, a, b});
             } else {
                 h->event_pool.push_back(a);
             }
@@ -269,16 +275,26 @@ struct Timer {
 };
 
 void collect_timers(fassmvs_handle *h) {
+    if (h->frame_t0) h->timeline.clear();
     for (auto &t : h->pending_timers) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
             h->stage_ms[t.stage] += ms;
             h->stage_n[t.stage] += 1;
+            if (t.level >= 0 && t.level < FASSMVS_MAX_LEVELS) {
+                h->stage_ms_lv[t.level][t.stage] += ms;
+                h->stage_n_lv[t.level][t.stage] += 1;
+            }
+            float st = 0.0f;
+            if (h->frame_t0 && hipEventElapsedTime(&st, h->frame_t0, t.a) == hipSuccess)
+                h->timeline.push_back(fassmvs_timeline_entry{t.stage, t.level, (double)st, (double)ms});
         }
         h->event_pool.push_back(t.a);
         h->event_pool.push_back(t.b);
     }
     h->pending_timers.clear();
+    if (h->frame_t0) h->event_pool.push_back(h->frame_t0);
+    h->frame_t0 = nullptr;
 }
 
 // Sweep tuning knob, read at every launch: FASSMVS_SWEEP_ROWS = 4 or 8 rows
@@ -868,7 +884,7 @@ size_t level_offset(const FramePlan &P, int l) {
 }
 
 fassmvs_status enqueue_pyramid(fassmvs_handle *h, const FramePlan &P) {
-    {
+    if (!h->prebuilt) {
         Timer t(h, ST_PYR);
         for (int i = 0; i <= P.n_views; ++i) {
             uint8_t *base = (uint8_t *)h->pyr[i].p;
@@ -1095,6 +1111,9 @@ fassmvs_status upload_frame(fassmvs_handle *h, const FramePlan &P, const fassmvs
             uint8_t *stg = pin + N0 * i;
             for (int y = 0; y < P.h; ++y) std::memcpy(stg + (size_t)y * P.w, im.pixels + (size_t)y * im.stride, P.w);
             HIPCHK(h, hipMemcpyAsync(dst, stg, N0, hipMemcpyHostToDevice, h->stream), "image upload");
+        } else if (h->prebuilt) {
+            HIPCHK(h, hipMemcpyAsync(dst, im.pixels, level_offset(P, P.n_levels), hipMemcpyDeviceToDevice, h->stream),
+                   "pyramid copy");
         } else {
             HIPCHK(h, hipMemcpy2DAsync(dst, P.w, im.pixels, im.stride, P.w, P.h, hipMemcpyDeviceToDevice, h->stream),
                    "image copy");
@@ -1112,6 +1131,7 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
     if ((st = enqueue_pyramid(h, P)) != FASSMVS_OK) return st;
     for (int l = P.n_levels - 1; l >= 0; --l) {
         const LevelPlan &L = P.lv[l];
+        h->cur_level = l;
         if ((st = enqueue_census(h, P, l)) != FASSMVS_OK) return st;
         {
             Timer t(h, ST_SWEEP);
@@ -1127,6 +1147,7 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
         if (st != FASSMVS_OK) return st;
         if ((st = enqueue_post(h, P, l)) != FASSMVS_OK) return st;
     }
+    h->cur_level = -1;
     return FASSMVS_OK;
 }
 
@@ -1420,6 +1441,78 @@ bool env_off(const char *name) {
 
 }  // namespace
 
+namespace {
+fassmvs_status submit_frame_locked(fassmvs_handle *h, const fassmvs_image *ref, const fassmvs_image *views,
+                                   const int8_t *view_side, int32_t n_views, const double K[9],
+                                   const fassmvs_plane_family *families, int32_t n_families, int32_t mem_kind,
+                                   uint64_t *ticket) {
+    if (h->latched) return FASSMVS_EDEVICE;
+    if (h->busy || h->batch_busy) return fail(h, FASSMVS_EBUSY, "a frame is in flight; poll it first");
+    if (!ticket) return fail(h, FASSMVS_EINVAL, "null ticket");
+    if (mem_kind != FASSMVS_MEM_HOST && mem_kind != FASSMVS_MEM_DEVICE) return fail(h, FASSMVS_EINVAL, "bad mem_kind");
+    HIPCHK(h, hipSetDevice(h->cfg.device), "hipSetDevice");
+    FramePlan &P = h->plan;
+    fassmvs_status st = make_plan(h, ref, views, view_side, n_views, K, families, n_families, P);
+    if (st != FASSMVS_OK) return st;
+    if ((st = alloc_frame(h, P)) != FASSMVS_OK) return st;
+    if (h->cfg.profile) {
+        if (h->frame_t0) h->event_pool.push_back(h->frame_t0);
+        h->frame_t0 = get_event(h);
+        if (h->frame_t0) HIPCHK(h, hipEventRecord(h->frame_t0, h->stream), "frame start event");
+    }
+    h->cur_level = -1;
+    if ((st = upload_frame(h, P, ref, views, mem_kind)) != FASSMVS_OK) return st;
+    if ((st = enqueue_frame(h, P)) != FASSMVS_OK) return st;
+    HIPCHK(h, hipMemcpyAsync(h->work_host, h->work_ctr.p, 8, hipMemcpyDeviceToHost, h->stream), "work counter");
+    HIPCHK(h, hipEventRecord(h->done, h->stream), "event record");
+    h->out_w = P.w;
+    h->out_h = P.h;
+    h->busy = true;
+    h->ticket = h->next_ticket++;
+    *ticket = h->ticket;
+    return FASSMVS_OK;
+}
+}  // namespace
+
+namespace fmvs {
+fassmvs_status handle_submit_pyramids(fassmvs_handle *h, const fassmvs_image *ref, const fassmvs_image *views,
+                                      const int8_t *view_side, int32_t n_views, const double K[9],
+                                      const fassmvs_plane_family *families, int32_t n_families, uint64_t *ticket) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (ref && ref->stride != ref->width) return fail(h, FASSMVS_EINVAL, "pyramid images are packed");
+    for (int k = 0; views && k < n_views; ++k)
+        if (views[k].stride != views[k].width) return fail(h, FASSMVS_EINVAL, "pyramid images are packed");
+    h->prebuilt = true;
+    fassmvs_status st =
+        submit_frame_locked(h, ref, views, view_side, n_views, K, families, n_families, FASSMVS_MEM_DEVICE, ticket);
+    h->prebuilt = false;
+    return st;
+}
+
+size_t pyramid_bytes(int w, int h, int n_levels) {
+    size_t b = 0;
+    for (int l = 0; l < n_levels; ++l) {
+        b += (size_t)w * h;
+        w /= 2;
+        h /= 2;
+    }
+    return b;
+}
+
+hipError_t pyramid_build(uint8_t *img, int w, int h, int n_levels, hipStream_t s) {
+    size_t off = 0;
+    for (int l = 0; l + 1 < n_levels; ++l) {
+        hipError_t e = launch_pyr_down(img + off, w, h, w, img + off + (size_t)w * h, s);
+        if (e != hipSuccess) return e;
+        off += (size_t)w * h;
+        w /= 2;
+        h /= 2;
+    }
+    return hipSuccess;
+}
+}  // namespace fmvs
+
 // =================================================================== C ABI
 
 extern "C" {
@@ -1582,26 +1675,10 @@ fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref,
                                     uint64_t *ticket) {
     if (!h) return FASSMVS_EINVAL;
     std::lock_guard<std::mutex> lk(h->mu);
-    if (h->latched) return FASSMVS_EDEVICE;
-    if (h->busy || h->batch_busy) return fail(h, FASSMVS_EBUSY, "a frame is in flight; poll it first");
-    if (!ticket) return fail(h, FASSMVS_EINVAL, "null ticket");
-    if (mem_kind != FASSMVS_MEM_HOST && mem_kind != FASSMVS_MEM_DEVICE) return fail(h, FASSMVS_EINVAL, "bad mem_kind");
-    HIPCHK(h, hipSetDevice(h->cfg.device), "hipSetDevice");
-    FramePlan &P = h->plan;
-    fassmvs_status st = make_plan(h, ref, views, view_side, n_views, K, families, n_families, P);
-    if (st != FASSMVS_OK) return st;
-    if ((st = alloc_frame(h, P)) != FASSMVS_OK) return st;
-    if ((st = upload_frame(h, P, ref, views, mem_kind)) != FASSMVS_OK) return st;
-    if ((st = enqueue_frame(h, P)) != FASSMVS_OK) return st;
-    HIPCHK(h, hipMemcpyAsync(h->work_host, h->work_ctr.p, 8, hipMemcpyDeviceToHost, h->stream), "work counter");
-    HIPCHK(h, hipEventRecord(h->done, h->stream), "event record");
-    h->out_w = P.w;
-    h->out_h = P.h;
-    h->busy = true;
-    h->ticket = h->next_ticket++;
-    *ticket = h->ticket;
-    return FASSMVS_OK;
+    h->prebuilt = false;
+    return submit_frame_locked(h, ref, views, view_side, n_views, K, families, n_families, mem_kind, ticket);
 }
+
 
 fassmvs_status fassmvs_submit_batch(fassmvs_handle *h, const fassmvs_frame *frames, int32_t n_frames, int32_t mem_kind,
                                     uint64_t *ticket) {
@@ -1957,6 +2034,7 @@ void fassmvs_destroy(fassmvs_handle *h) {
             hipEventDestroy(t.b);
         }
         for (auto e : h->event_pool) hipEventDestroy(e);
+        if (h->frame_t0) hipEventDestroy(h->frame_t0);
         if (h->done) hipEventDestroy(h->done);
         if (h->own_stream) hipStreamDestroy(h->stream);
     }
@@ -1978,12 +2056,37 @@ fassmvs_status fassmvs_stage_times(fassmvs_handle *h, double *ms, int32_t *count
     return FASSMVS_OK;
 }
 
+fassmvs_status fassmvs_stage_times_level(fassmvs_handle *h, int32_t level, double *ms, int32_t *counts, int32_t n) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (level < 0 || level >= FASSMVS_MAX_LEVELS) return fail(h, FASSMVS_EINVAL, "level must be 0..4");
+    for (int i = 0; i < n && i < ST_COUNT; ++i) {
+        if (ms) ms[i] = h->stage_ms_lv[level][i];
+        if (counts) counts[i] = h->stage_n_lv[level][i];
+    }
+    return FASSMVS_OK;
+}
+
+fassmvs_status fassmvs_frame_timeline(fassmvs_handle *h, fassmvs_timeline_entry *out, int32_t max_entries,
+                                      int32_t *n_entries) {
+    if (!h || !n_entries || max_entries < 0 || (max_entries > 0 && !out)) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    const int n = (int)h->timeline.size();
+    for (int i = 0; i < n && i < max_entries; ++i) out[i] = h->timeline[i];
+    *n_entries = n;
+    return FASSMVS_OK;
+}
+
 fassmvs_status fassmvs_reset_stage_times(fassmvs_handle *h) {
     if (!h) return FASSMVS_EINVAL;
     std::lock_guard<std::mutex> lk(h->mu);
     for (int i = 0; i < ST_COUNT; ++i) {
         h->stage_ms[i] = 0;
         h->stage_n[i] = 0;
+        for (int l = 0; l < FASSMVS_MAX_LEVELS; ++l) {
+            h->stage_ms_lv[l][i] = 0;
+            h->stage_n_lv[l][i] = 0;
+        }
     }
     return FASSMVS_OK;
 }
@@ -1994,6 +2097,8 @@ fassmvs_status fassmvs_frame_work(fassmvs_handle *h, double *out, int32_t n) {
     if (!h || !out) return FASSMVS_EINVAL;
     std::lock_guard<std::mutex> lk(h->mu);
     for (int i = 0; i < n && i < 4; ++i) out[i] = h->last_work[i];
+    for (int l = 0; l < FASSMVS_MAX_LEVELS && 4 + l < n; ++l)
+        out[4 + l] = l < h->plan.n_levels ? (double)h->plan.lv[l].w * h->plan.lv[l].h * h->plan.lv[l].D : 0.0;
     return FASSMVS_OK;
 }
 

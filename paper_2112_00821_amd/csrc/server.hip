@@ -11,7 +11,9 @@
 // queued frames and collects finished ones; submit and result calls only
 // touch the queues.  Keyframe images stay on the device (pooled image
 // buffers, held by reference counts of the frames that use them and of the
-// keyframe list).
+// keyframe list), each with its whole pyramid, built once when the image
+// arrives, so the frames that match against it copy its levels instead of
+// rebuilding them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,7 +35,10 @@
 using fmvs::handle_growth;
 using fmvs::handle_held;
 using fmvs::handle_set_exact_growth;
+using fmvs::handle_submit_pyramids;
 using fmvs::handle_trim;
+using fmvs::pyramid_build;
+using fmvs::pyramid_bytes;
 
 namespace {
 
@@ -309,8 +314,8 @@ bool admit_one(fassmvs_server *s, std::unique_lock<std::mutex> &lk) {
     hipStreamWaitEvent(free_slot->stream, req.img->b.ready, 0);
     for (auto &v : req.views) hipStreamWaitEvent(free_slot->stream, v.img->b.ready, 0);
     uint64_t ticket = 0;
-    fassmvs_status rc = fassmvs_submit_frame(free_slot->h, &ref, views, side, nv, K, fams.data(),
-                                             (int32_t)fams.size(), FASSMVS_MEM_DEVICE, &ticket);
+    fassmvs_status rc =
+        handle_submit_pyramids(free_slot->h, &ref, views, side, nv, K, fams.data(), (int32_t)fams.size(), &ticket);
     lk.lock();
     if (rc != FASSMVS_OK) {
         give_maps(res);
@@ -470,6 +475,7 @@ fassmvs_status fassmvs_server_submit(fassmvs_server *s, int32_t stream_id, const
     // of the stream that takes it as a keyframe finds it there
     ImageBuf b;
     const size_t N = (size_t)st->w * st->h;
+    const size_t NP = pyramid_bytes(st->w, st->h, s->cfg.n_levels);   // the image and its coarser levels
     {
         std::lock_guard<std::mutex> lk(s->pools.mu);
         auto &v = s->pools.img[N];
@@ -479,7 +485,7 @@ fassmvs_status fassmvs_server_submit(fassmvs_server *s, int32_t stream_id, const
         }
     }
     if (!b.p) {
-        if (hipMalloc(&b.p, N) != hipSuccess || hipHostMalloc(&b.stage, N) != hipSuccess ||
+        if (hipMalloc(&b.p, NP) != hipSuccess || hipHostMalloc(&b.stage, N) != hipSuccess ||
             hipEventCreateWithFlags(&b.ready, hipEventDisableTiming) != hipSuccess) {
             (void)hipGetLastError();
             if (b.p) hipFree(b.p);
@@ -495,6 +501,7 @@ fassmvs_status fassmvs_server_submit(fassmvs_server *s, int32_t stream_id, const
     img->n = N;
     img->pools = &s->pools;
     if (hipMemcpyAsync(b.p, b.stage, N, hipMemcpyHostToDevice, s->upload) != hipSuccess ||
+        pyramid_build(b.p, st->w, st->h, s->cfg.n_levels, s->upload) != hipSuccess ||
         hipEventRecord(b.ready, s->upload) != hipSuccess)
         return sfail(s, FASSMVS_EDEVICE, "image upload failed");
     Request req;

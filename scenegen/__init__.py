@@ -607,6 +607,56 @@ def served_stream(seed: int, w: int, h: int, n_frames: int, spacing: float = 0.5
 SERVED_STREAMS = [(200, 960, 540), (201, 1280, 720), (202, 1920, 1080), (203, 2704, 1520)]
 
 
+def served_path(seed: int, w: int, h: int, n_frames: int, spacing: float = 0.5, planes: int = 128,
+                n_boxes: int = 20, n_roofs: int = 5):
+    """A served stream without its images: the scene, intrinsics and the
+    poses of n_frames along a smooth oblique flight path (spacing metres
+    apart: 5 m/s at 10 Hz), centred on the scene; each image is rendered by
+    served_image (independently, so frames can be rendered in parallel)."""
+    rng = np.random.default_rng(seed)
+    fx = 1500.0 * w / 1920.0
+    height, pitch = 60.0, 45.0
+    K = _K(fx, fx, w / 2.0, h / 2.0)
+    heading = float(rng.uniform(0.0, 360.0))
+    C_ref = np.array([0.0, 0.0, height])
+    R0, t0 = pose_from_heading(C_ref, heading, pitch)
+    Kinv = np.linalg.inv(K)
+    pts = []
+    for (u, v) in ((0, 0), (w, 0), (0, h), (w, h), (w / 2, h / 2)):
+        d = R0.T @ (Kinv @ np.array([u, v, 1.0]))
+        pts.append(C_ref + (-height / d[2]) * d)
+    pts = np.array(pts)
+    region = (pts[:, 0].min() * 0.8, pts[:, 0].max() * 0.8, pts[:, 1].min() * 0.8, pts[:, 1].max() * 0.8)
+    cx, cy = pts[4, 0], pts[4, 1]
+    half = 0.35 * min(region[1] - region[0], region[3] - region[2])
+    boxes = _place_boxes(rng, n_boxes, (cx - half, cx + half, cy - half, cy + half), (8.0, 25.0), (5.0, 30.0),
+                         n_roofs)
+    texel = float(np.median(np.linalg.norm(pts[:4] - C_ref, axis=1))) * 0.75 / fx
+    centers = _flight(rng, C_ref, heading, n_frames, n_frames // 2, (spacing, spacing))
+    poses = [pose_from_heading(C, heading + rng.uniform(-1.0, 1.0), pitch + rng.uniform(-1.0, 1.0),
+                               rng.uniform(-1.0, 1.0)) for C in centers]
+    fam = [dict(n=(0.0, 0.0, -1.0), delta_min=20.0, delta_max=400.0, count=planes)]
+    params = _params(n_levels=3, census_w=9, census_h=7, p1=24, p2_mode=1, sgm_variant=1, window_labels=planes)
+    return dict(seed=seed, K=K, width=w, height=h, scene=Scene(boxes), texel=texel, poses=poses, families=fam,
+                params=params, noise_std=0.05 * 255.0)
+
+
+_TEX_CACHE = {}
+
+
+def served_image(path: dict, i: int) -> np.ndarray:
+    """Image i of a served stream (its noise drawn from a generator of its
+    own, so any subset renders the same)."""
+    key = path["seed"]
+    if key not in _TEX_CACHE:
+        _TEX_CACHE.clear()
+        _TEX_CACHE[key] = noise_texture(key + 1000, size=2048)
+    R, t = path["poses"][i]
+    img, _ = _frame(path["scene"], path["K"], R, t, path["width"], path["height"], _TEX_CACHE[key], path["texel"],
+                    path["noise_std"], np.random.default_rng([path["seed"], i]))
+    return img
+
+
 def with_cross_ratio_counts(wl):
     """The same bundle with every family's coarsest plane count left to the
     cross-ratio construction (count 0)."""

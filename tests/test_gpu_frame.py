@@ -110,3 +110,26 @@ def test_hbm_budget_rejects_large_frame(fm):
         with pytest.raises(fm.FassmvsError) as e:
             h.run_frame(wl)
         assert e.value.status == fm.ENOMEM
+
+
+def test_stage_times_per_level_and_timeline(fm):
+    wl = scenegen.make_workload("config2_small")
+    cfg = fm.config_from_params(wl["params"], profile=1)
+    with fm.Handle(cfg) as h:
+        h.run_frame(wl)
+        h.reset_stage_times()
+        h.run_frame(wl)
+        tot = h.stage_times()
+        per = [h.stage_times_level(l) for l in range(wl["params"]["n_levels"])]
+        for st in ("census", "sweep", "sgm_dirs", "sgm_wta", "refine", "normals"):
+            assert all(p[st][1] == 1 for p in per), st            # one timed launch group per level
+            assert abs(sum(p[st][0] for p in per) - tot[st][0]) <= 1e-6 * max(1.0, tot[st][0])
+        assert per[0]["seed"][1] == 0 and per[1]["seed"][1] == 1  # seeds come from the coarser level
+        tl = h.frame_timeline()
+        assert [s for s, _, _, _ in tl][:2] == ["upload", "pyramid"]
+        assert {lv for _, lv, _, _ in tl} == {-1, 0, 1, 2}
+        starts = [a for _, _, a, _ in tl]
+        assert all(b >= a - 1e-3 for a, b in zip(starts, starts[1:]))   # one stream: in enqueue order
+        assert all(d >= 0 for _, _, _, d in tl)
+        w = h.frame_work()
+        assert sum(w["pixel_hyp_level"]) == w["pixel_hyp"]
