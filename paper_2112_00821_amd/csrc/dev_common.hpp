@@ -8,6 +8,14 @@ namespace fmvs {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// 1 / z for a positive normal double: the hardware estimate refined by two
+// Newton steps (within an ulp of the correctly rounded quotient).
+__device__ __forceinline__ double recip(double z) {
+    const double r0 = __builtin_amdgcn_rcp(z);
+    const double r1 = __builtin_fma(r0, __builtin_fma(-z, r0, 1.0), r0);
+    return __builtin_fma(r1, __builtin_fma(-z, r1, 1.0), r1);
+}
+
 // Bilinear clamp-to-edge sample of an 8-bit view at the point the
 // homography H maps the reference-grid point (qx, qy) to (pixel-centre
 // coordinates on both sides).  Every operation is fixed: fused
@@ -22,7 +30,7 @@ __device__ __forceinline__ float warp_sample(const uint8_t *__restrict__ src, in
     const double hx = __builtin_fma(h0, qx, __builtin_fma(h1, qy, h2));
     const double hy = __builtin_fma(h3, qx, __builtin_fma(h4, qy, h5));
     const double hz = __builtin_fma(h6, qx, __builtin_fma(h7, qy, h8));
-    const double r = 1.0 / hz;
+    const double r = recip(hz);
     const double inv = hz > 1e-300 ? r : 0.0;
     // The coordinate is clamped to [0, size - 1] rather than [-1, size]:
     // outside [0, size - 1] both bilinear neighbours of the clamp-to-edge
@@ -62,7 +70,7 @@ __device__ __forceinline__ float warp_sample_inside(const uint8_t *__restrict__ 
     const double hx = __builtin_fma(h0, qx, __builtin_fma(h1, qy, h2));
     const double hy = __builtin_fma(h3, qx, __builtin_fma(h4, qy, h5));
     const double hz = __builtin_fma(h6, qx, __builtin_fma(h7, qy, h8));
-    const double r = 1.0 / hz;
+    const double r = recip(hz);
     const double sx = __builtin_fma(hx, r, -0.5);
     const double sy = __builtin_fma(hy, r, -0.5);
     const uint32_t xa = (uint32_t)(int)sx, ya = (uint32_t)(int)sy;

@@ -44,3 +44,36 @@ def first_mismatch(got, exp):
         return None
     i = tuple(int(v) for v in d[0])
     return i, got[i], exp[i]
+
+
+# The sweep's reciprocal of the homogeneous coordinate is the hardware
+# estimate refined by two Newton steps: within an ulp of the correctly
+# rounded quotient the oracle takes.  A warped sample can then differ from
+# the oracle's in the last float bit (rarely: about one sample in a million),
+# and a census bit or an NCC rounding only flips at a near tie with it, so
+# costs the kernel computes from images agree with the oracle's on all but a
+# vanishing fraction of entries.  Costs from the oracle's own warped images
+# stay bit-exact.
+FROM_IMAGES_MIN_SAME = 0.9999
+
+
+def assert_costs_from_images(got, exp, what=""):
+    """Cost entries computed from images (the kernel warps): identical on
+    >= FROM_IMAGES_MIN_SAME of the entries; prints the differing count."""
+    same = got == exp
+    n_diff = int(same.size - np.count_nonzero(same))
+    if n_diff:
+        print(f"[costs from images] {what}: {n_diff} of {same.size} entries differ; first {first_mismatch(got, exp)}",
+              flush=True)
+    assert same.mean() >= FROM_IMAGES_MIN_SAME, (what, n_diff, first_mismatch(got, exp))
+
+
+# Warped intensities: within 1e-4 on [0, 1] of the oracle's, and identical on
+# all but a vanishing fraction of samples (see above).
+WARP_TOL = 1e-4 * 255.0
+
+
+def assert_warp_close(got, exp, what=""):
+    d = np.abs(got.astype(np.float64) - exp.astype(np.float64))
+    assert d.max() <= WARP_TOL, (what, float(d.max()) / 255.0)
+    assert np.mean(got == exp) >= 0.999, (what, float(np.mean(got == exp)))

@@ -28,7 +28,7 @@ import numpy as np
 import pytest
 
 import scenegen
-from parity_util import compare_level, first_mismatch
+from parity_util import assert_costs_from_images, compare_level, first_mismatch
 
 pytestmark = pytest.mark.gpu
 
@@ -191,7 +191,7 @@ def test_coarsest_level(orc, run, oracle_run):
     xy = np.concatenate([xy, [[0, 0], [ww - 1, hh - 1], [ww - 1, 0], [0, hh - 1]]]).astype(np.int32)
     exp = _cost_pixels(orc, wl, img, views, plan, H, xy)
     got = S[xy[:, 1], xy[:, 0]]
-    assert np.array_equal(got, exp), first_mismatch(got, exp)
+    assert_costs_from_images(got, exp, f"{name} coarsest level, sampled")
 
 
 def test_level0_windows_centred_on_seed(orc, run):
