@@ -17,6 +17,11 @@ fassmvs_status handle_growth(fassmvs_handle *h, const fassmvs_image *ref, const 
                              const fassmvs_plane_family *families, int32_t n_families, uint64_t *grow);
 // Free every device buffer of a handle with no frame in flight.
 void handle_trim(fassmvs_handle *h);
+// Bytes the handle would grow by to hold any frame of a stream (w x hgt
+// images, n_views views on one side, these intrinsics and families), and
+// growing it to that (apply); a handle with no frame in flight.
+fassmvs_status handle_reserve(fassmvs_handle *h, int w, int hgt, int n_views, const double K[9],
+                              const fassmvs_plane_family *families, int n_families, bool apply, uint64_t *grow);
 // Bytes of an image's whole pyramid (levels halved with integer division,
 // level 0 first, each level's rows packed) for n_levels levels.
 size_t pyramid_bytes(int w, int h, int n_levels);

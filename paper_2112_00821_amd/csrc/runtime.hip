@@ -1920,6 +1920,44 @@ fassmvs_status handle_growth(fassmvs_handle *h, const fassmvs_image *ref, const 
     return FASSMVS_OK;
 }
 
+fassmvs_status handle_reserve(fassmvs_handle *h, int w, int hgt, int n_views, const double K[9],
+                              const fassmvs_plane_family *families, int n_families, bool apply, uint64_t *grow) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (h->busy || h->batch_busy) return fail(h, FASSMVS_EBUSY, "frame in flight");
+    if (n_views < 1 || n_views > kMaxViews) return fail(h, FASSMVS_EINVAL, "n_views must be 1..8");
+    // a bundle of that shape: the buffers depend on sizes, views and plane
+    // counts, not on the poses (identity poses; pixels are not read)
+    static const uint8_t dummy = 0;
+    fassmvs_image ims[kMaxViews + 1];
+    int8_t side[kMaxViews];
+    for (int i = 0; i <= n_views; ++i) {
+        std::memset(&ims[i], 0, sizeof(ims[i]));
+        ims[i].pixels = &dummy;
+        ims[i].width = w;
+        ims[i].height = hgt;
+        ims[i].stride = w;
+        ims[i].R[0] = ims[i].R[4] = ims[i].R[8] = 1.0;
+        if (i < n_views) side[i] = -1;
+    }
+    FramePlan P;
+    fassmvs_status st = make_plan(h, &ims[0], &ims[1], side, n_views, K, families, n_families, P);
+    if (st != FASSMVS_OK) return st;
+    std::vector<std::pair<DevBuf *, size_t>> bufs;
+    frame_buffers(h, P, bufs);
+    uint64_t g = 0;
+    for (auto &b : bufs) {
+        const size_t need = b.second == 0 ? 256 : b.second;
+        if (b.first->bytes < need) g += (h->exact_growth ? need : need + need / 8) - b.first->bytes;
+    }
+    if (grow) *grow = g;
+    if (apply && g > 0) {
+        HIPCHK(h, hipSetDevice(h->cfg.device), "hipSetDevice");
+        HIPCHK(h, hipStreamSynchronize(h->stream), "reserve");
+        return alloc_frame(h, P);
+    }
+    return FASSMVS_OK;
+}
+
 void handle_trim(fassmvs_handle *h) {
     std::lock_guard<std::mutex> lk(h->mu);
     if (h->busy) return;

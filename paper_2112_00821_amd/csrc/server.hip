@@ -34,6 +34,7 @@
 
 using fmvs::handle_growth;
 using fmvs::handle_held;
+using fmvs::handle_reserve;
 using fmvs::handle_set_exact_growth;
 using fmvs::handle_submit_pyramids;
 using fmvs::handle_trim;
@@ -187,6 +188,7 @@ struct fassmvs_server {
     std::string err;
     std::thread worker;
     size_t in_flight = 0;
+    bool reserve_pending = false;   // a stream opened: size the slots for it when the device is idle
     hipStream_t upload = nullptr, fetch = nullptr;   // non-blocking streams for image uploads and result copies
     std::mutex fetch_mu;
 };
@@ -365,12 +367,37 @@ bool collect(fassmvs_server *s, std::unique_lock<std::mutex> &lk) {
     return any;
 }
 
+// Grow every slot to hold any frame of every open stream (a bundle of the
+// stream's size with its full keyframe count), within the budget, while no
+// frame is in flight: afterwards a frame never waits for the device to go
+// idle before its slot can grow (growth waits for that, since freeing device
+// memory synchronises the device).  lk held.
+void reserve_slots(fassmvs_server *s) {
+    if (!s->reserve_pending || s->in_flight > 0) return;
+    s->reserve_pending = false;
+    for (auto &kv : s->streams) {
+        const Stream &st = *kv.second;
+        if (st.closed) continue;
+        for (auto &sl : s->slots) {
+            uint64_t g = 0, held = 0;
+            if (handle_reserve(sl.h, st.w, st.h, st.max_kf, st.K, st.fams.data(), (int32_t)st.fams.size(), false,
+                               &g) != FASSMVS_OK || g == 0)
+                continue;
+            for (auto &o : s->slots) held += handle_held(o.h);
+            if (held + g > s->budget) continue;
+            (void)handle_reserve(sl.h, st.w, st.h, st.max_kf, st.K, st.fams.data(), (int32_t)st.fams.size(), true,
+                                 &g);
+        }
+    }
+}
+
 void worker_loop(fassmvs_server *s) {
     hipSetDevice(s->cfg.device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         if (s->stop && s->queue.empty() && s->in_flight == 0) break;
         bool progress = collect(s, lk);
+        reserve_slots(s);
         while (admit_one(s, lk)) progress = true;
         if (!progress) {
             if (s->in_flight > 0)
@@ -448,10 +475,14 @@ fassmvs_status fassmvs_server_open_stream(fassmvs_server *s, const double K[9], 
     st->max_kf = max_keyframes;
     st->min_baseline = min_baseline;
     st->pools = &s->pools;
-    std::lock_guard<std::mutex> lk(s->mu);
-    st->id = s->next_stream++;
-    *stream_id = st->id;
-    s->streams[st->id] = std::move(st);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        st->id = s->next_stream++;
+        *stream_id = st->id;
+        s->streams[st->id] = std::move(st);
+        s->reserve_pending = true;
+    }
+    s->cv_work.notify_all();
     return FASSMVS_OK;
 }
 
