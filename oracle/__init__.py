@@ -22,7 +22,13 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fassmvs_oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# FASSMVS_ORACLE_SANITIZE=1: an AddressSanitizer + UndefinedBehaviorSanitizer
+# build (the process must preload the ASan runtime; see
+# tests/test_sanitizers.py)
+_SANITIZE = os.environ.get("FASSMVS_ORACLE_SANITIZE", "0") not in ("", "0")
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+              "-fno-sanitize-recover=undefined"]
 
 DIRS = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1)]
 
@@ -31,7 +37,8 @@ def build(force: bool = False) -> str:
     """Compile the oracle with g++ (no fused multiply-add, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+        opt = _SAN_FLAGS if _SANITIZE else ["-O2"]
+        subprocess.check_call(["g++", *opt, "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
                                "-fno-fast-math", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
