@@ -57,34 +57,6 @@ def _compile(unit) -> str:
     return obj
 
 
-# Host-runtime check under host-side sanitizers: runtime.hip and server.hip
-# rebuilt with AddressSanitizer and UndefinedBehaviorSanitizer on their host
-# code only (device code is never instrumented), linked with the kernel
-# objects and a driver (csrc/host_check.cpp) into one executable.
-HOST_CHECK = os.path.join(PKG, "fassmvs_host_check")
-SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
-       "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
-
-
-def build_host_check(objs, verbose: bool = False) -> str:
-    san_dir = os.path.join(BUILD, "san")
-    os.makedirs(san_dir, exist_ok=True)
-    host = {"runtime.hip": "runtime_san", "server.hip": "server_san", "host_check.cpp": "host_check"}
-    units = [(src, os.path.join("san", name), SAN) for src, name in host.items()]
-    with ThreadPoolExecutor(max_workers=len(units)) as ex:
-        san_objs = list(ex.map(_compile, units))
-    plain = [o for o in objs if os.path.basename(o) not in ("runtime.o", "server.o")]
-    tmp = HOST_CHECK + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", *SAN, "-o", tmp, *san_objs, *plain, "-Wl,-rpath,/opt/rocm/lib"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"host check link failed:\n{r.stderr[-4000:]}")
-    os.replace(tmp, HOST_CHECK)
-    if verbose:
-        print("built", HOST_CHECK)
-    return HOST_CHECK
-
-
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     units = _units()
@@ -101,7 +73,6 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
-    build_host_check(objs, verbose)
     return LIB
 
 

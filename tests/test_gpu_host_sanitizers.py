@@ -1,7 +1,7 @@
 """The library's host runtime under AddressSanitizer and
-UndefinedBehaviorSanitizer: `fassmvs_host_check` (built by the package's
-build with both sanitizers on the host code of runtime.hip and server.hip;
-device code is not instrumented) drives frames with host and device
+UndefinedBehaviorSanitizer: `fassmvs_host_check` (built by
+paper_2112_00821_amd/build_host_check.py with both sanitizers on the host
+code of runtime.hip and server.hip; device code is not instrumented) drives frames with host and device
 buffers, explicit plane lists and depth ranges, a batch of uneven frames,
 the served form with two streams, the plane-set helpers and error paths on
 device 0.  Any sanitizer report aborts it."""
@@ -17,7 +17,7 @@ EXE = os.path.join(ROOT, "paper_2112_00821_amd", "fassmvs_host_check")
 
 
 def test_host_runtime_under_asan_and_ubsan():
-    assert os.path.exists(EXE), "fassmvs_host_check is not built (paper_2112_00821_amd/build.py builds it)"
+    assert os.path.exists(EXE), "fassmvs_host_check is not built (paper_2112_00821_amd/build_host_check.py builds it)"
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:verify_asan_link_order=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     print("running", EXE, flush=True)
