@@ -148,6 +148,7 @@ struct fassmvs_handle {
         uint64_t gen = 0;
     };
     std::map<std::string, BatchGraph> graphs;
+    std::map<std::string, BatchGraph> frame_graphs;   // single frames (profile off), by plan shape and values
     struct Tuning {
         int rpt = 8, target = 8192, groups = 1;
         bool graph = true;
@@ -1151,6 +1152,83 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
     return FASSMVS_OK;
 }
 
+constexpr size_t kMaxFrameGraphs = 8;   // captured frame graphs kept per handle
+
+// A frame plan's shape and the values its launches take by value (the key
+// of a captured frame graph), with the launch-time tuning knobs.
+std::string plan_signature(const FramePlan &P) {
+    std::string sig;
+    auto raw = [&sig](const void *p, size_t b) { sig.append((const char *)p, b); };
+    const char *knobs[] = {"FASSMVS_SWEEP_ROWS", "FASSMVS_SWEEP_BLOCKS", "FASSMVS_SGM_UNPACKED"};
+    for (const char *k : knobs) {
+        const char *e = std::getenv(k);
+        sig += std::string(k) + "=" + (e ? e : "") + ";";
+    }
+    raw(&P.n_levels, sizeof(int));
+    raw(&P.n_views, sizeof(int));
+    raw(&P.w, sizeof(int));
+    raw(&P.h, sizeof(int));
+    raw(&P.F, sizeof(int));
+    raw(&P.nL, sizeof(int));
+    raw(&P.nR, sizeof(int));
+    raw(P.side, sizeof(int) * P.n_views);
+    raw(P.fam_n, sizeof(double) * 3 * P.F);
+    raw(&P.p1, sizeof(int));
+    raw(P.lut, sizeof(P.lut));
+    for (int l = 0; l < P.n_levels; ++l) {
+        const LevelPlan &L = P.lv[l];
+        raw(&L.w, sizeof(int));
+        raw(&L.h, sizeof(int));
+        raw(&L.D, sizeof(int));
+        raw(&L.sumG, sizeof(int));
+        raw(L.G, sizeof(int) * L.F);
+        raw(L.W, sizeof(int) * L.F);
+        raw(L.step, sizeof(double) * L.F);
+        raw(L.Kinv, sizeof(L.Kinv));
+        const char flags[2] = {(char)L.windows, (char)L.sn};
+        raw(flags, 2);
+        raw(&L.h_off, sizeof(size_t));
+        raw(&L.d_off, sizeof(size_t));
+        raw(&L.i_off, sizeof(size_t));
+    }
+    return sig;
+}
+
+// Enqueue the frame's launches: replayed from a captured graph when the
+// handle does not profile (HIP-event timers cannot sit in a graph) and
+// FASSMVS_FRAME_GRAPH is not 0; launch by launch otherwise.
+fassmvs_status enqueue_frame_graph(fassmvs_handle *h, const FramePlan &P) {
+    const char *e = std::getenv("FASSMVS_FRAME_GRAPH");
+    if (h->cfg.profile || (e && std::atoi(e) == 0)) return enqueue_frame(h, P);
+    const std::string key = plan_signature(P);
+    if (h->frame_graphs.size() >= kMaxFrameGraphs && !h->frame_graphs.count(key)) {
+        for (auto &kv : h->frame_graphs)
+            if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+        h->frame_graphs.clear();
+    }
+    auto &g = h->frame_graphs[key];
+    if (!g.exec || g.gen != h->gen) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed), "frame graph capture");
+        fassmvs_status st = enqueue_frame(h, P);
+        hipGraph_t graph = nullptr;
+        hipError_t ee = hipStreamEndCapture(h->stream, &graph);
+        if (st != FASSMVS_OK) {
+            if (graph) hipGraphDestroy(graph);
+            h->frame_graphs.erase(key);
+            return st;
+        }
+        HIPCHK(h, ee, "frame graph capture");
+        ee = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        HIPCHK(h, ee, "frame graph instantiation");
+        g.gen = h->gen;
+    }
+    HIPCHK(h, hipGraphLaunch(g.exec, h->stream), "frame graph launch");
+    return FASSMVS_OK;
+}
+
 fassmvs_status copy_out(fassmvs_handle *h, void *dst, const void *src, size_t bytes, int mem_kind) {
     if (!dst) return FASSMVS_OK;
     hipMemcpyKind k = mem_kind == FASSMVS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1462,7 +1540,7 @@ fassmvs_status submit_frame_locked(fassmvs_handle *h, const fassmvs_image *ref, 
     }
     h->cur_level = -1;
     if ((st = upload_frame(h, P, ref, views, mem_kind)) != FASSMVS_OK) return st;
-    if ((st = enqueue_frame(h, P)) != FASSMVS_OK) return st;
+    if ((st = enqueue_frame_graph(h, P)) != FASSMVS_OK) return st;
     HIPCHK(h, hipMemcpyAsync(h->work_host, h->work_ctr.p, 8, hipMemcpyDeviceToHost, h->stream), "work counter");
     HIPCHK(h, hipEventRecord(h->done, h->stream), "event record");
     h->out_w = P.w;
@@ -2062,6 +2140,8 @@ void fassmvs_destroy(fassmvs_handle *h) {
             release(L.label); release(L.fam); release(L.offs); release(L.dI); release(L.dbar); release(L.nbar);
         }
         for (auto &g : h->graphs)
+            if (g.second.exec) hipGraphExecDestroy(g.second.exec);
+        for (auto &g : h->frame_graphs)
             if (g.second.exec) hipGraphExecDestroy(g.second.exec);
         release(h->batch_dev);
         if (h->batch_stage) hipHostFree(h->batch_stage);

@@ -133,3 +133,23 @@ def test_stage_times_per_level_and_timeline(fm):
         assert all(d >= 0 for _, _, _, d in tl)
         w = h.frame_work()
         assert sum(w["pixel_hyp_level"]) == w["pixel_hyp"]
+
+
+def test_frame_graph_replay_equals_launches(fm, monkeypatch):
+    """Frames replayed from their captured graph (handles that do not
+    profile) give the maps of the launch-by-launch path, over repeated
+    frames and across a change of shape and back."""
+    a = scenegen.make_workload("config2_small")
+    b = scenegen.make_workload("config2_ragged")
+    runs = {}
+    for graph in ("1", "0"):
+        monkeypatch.setenv("FASSMVS_FRAME_GRAPH", graph)
+        out = []
+        with fm.Handle(fm.config_from_params(a["params"], profile=0)) as h:
+            for wl in (a, a, b, a):
+                out.append(h.run_frame(wl))
+        runs[graph] = out
+    for i, (x, y) in enumerate(zip(runs["1"], runs["0"])):
+        for k in ("depth", "normal", "conf"):
+            assert np.array_equal(x[k], y[k]), (i, k)
+    assert np.array_equal(runs["1"][0]["depth"], runs["1"][1]["depth"])
