@@ -162,6 +162,18 @@ fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref,
                                     const fassmvs_plane_family *families, int32_t n_families,
                                     int32_t mem_kind, uint64_t *ticket);
 
+/* fassmvs_submit_frame with the reference view's depth range [d_min, d_max]
+ * given once for the bundle (the problem statement's depth range): every
+ * family with no explicit list and delta_min = delta_max = 0 takes its
+ * distance range from the bounding planes of that depth range (Sec. on
+ * bounding planes; as depth_min / depth_max of the family).  EINVAL when
+ * 0 < d_min < d_max does not hold.  Per-stream state (keyframes, their
+ * pyramids) belongs to the served form, whose calls take a stream id. */
+fassmvs_status fassmvs_submit_frame_range(fassmvs_handle *h, const fassmvs_image *ref, const fassmvs_image *views,
+                                          const int8_t *view_side, int32_t n_views, const double K[9], double d_min,
+                                          double d_max, const fassmvs_plane_family *families, int32_t n_families,
+                                          int32_t mem_kind, uint64_t *ticket);
+
 /* Collect a frame's maps.  depth: W*H floats; normal: W*H*3 floats; confidence:
  * W*H floats in [0, 1]; any may be NULL.  mem_kind says whether the output
  * pointers are host or device memory.  wait_ms: 0 non-blocking, -1 blocking,

@@ -80,6 +80,7 @@ def _declare(L):
         "fassmvs_submit_frame": (st, [vp, vp, vp, vp, i32, vp, vp, i32, i32, vp]),
         "fassmvs_poll": (st, [vp, u64, vp, vp, vp, i32, i32]),
         "fassmvs_submit_batch": (st, [vp, vp, i32, i32, vp]),
+        "fassmvs_submit_frame_range": (st, [vp, vp, vp, vp, i32, vp, dbl, dbl, vp, i32, i32, vp]),
         "fassmvs_poll_batch": (st, [vp, u64, i32, vp, vp, vp, i32, i32]),
         "fassmvs_batch_tuning": (st, [vp, vp, vp, vp, vp, vp]),
         "fassmvs_destroy": (None, [vp]),
@@ -431,6 +432,16 @@ class Handle:
         t = C.c_uint64()
         self._check(lib().fassmvs_submit_frame(self.h, C.byref(r), vs, sd, len(views), Kc, fams, len(families),
                                                mem_kind, C.byref(t)))
+        return t.value
+
+    def submit_frame_range(self, ref, views, side, K, d_min, d_max, families, mem_kind=MEM_HOST):
+        """submit_frame with one depth range for the bundle (families without
+        a distance range or list take it through their bounding planes)."""
+        keep = []
+        r, vs, sd, Kc, fams = self._frame_args(ref, views, side, K, families, keep)
+        t = C.c_uint64()
+        self._check(lib().fassmvs_submit_frame_range(self.h, C.byref(r), vs, sd, len(views), Kc, float(d_min),
+                                                     float(d_max), fams, len(families), mem_kind, C.byref(t)))
         return t.value
 
     def submit_batch(self, workloads, mem_kind=MEM_HOST):

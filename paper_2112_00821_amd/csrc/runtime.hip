@@ -1757,6 +1757,26 @@ fassmvs_status fassmvs_submit_frame(fassmvs_handle *h, const fassmvs_image *ref,
     return submit_frame_locked(h, ref, views, view_side, n_views, K, families, n_families, mem_kind, ticket);
 }
 
+fassmvs_status fassmvs_submit_frame_range(fassmvs_handle *h, const fassmvs_image *ref, const fassmvs_image *views,
+                                          const int8_t *view_side, int32_t n_views, const double K[9], double d_min,
+                                          double d_max, const fassmvs_plane_family *families, int32_t n_families,
+                                          int32_t mem_kind, uint64_t *ticket) {
+    if (!h) return FASSMVS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (!(d_min > 0.0) || !(d_max > d_min) || !std::isfinite(d_max))
+        return fail(h, FASSMVS_EINVAL, "depth range must satisfy 0 < d_min < d_max");
+    if (!families || n_families < 1 || n_families > kMaxFam) return fail(h, FASSMVS_EINVAL, "n_families must be 1..8");
+    fassmvs_plane_family fams[kMaxFam];
+    for (int f = 0; f < n_families; ++f) {
+        fams[f] = families[f];
+        if (!fams[f].delta && fams[f].delta_min == 0.0 && fams[f].delta_max == 0.0) {
+            fams[f].depth_min = d_min;
+            fams[f].depth_max = d_max;
+        }
+    }
+    h->prebuilt = false;
+    return submit_frame_locked(h, ref, views, view_side, n_views, K, fams, n_families, mem_kind, ticket);
+}
 
 fassmvs_status fassmvs_submit_batch(fassmvs_handle *h, const fassmvs_frame *frames, int32_t n_frames, int32_t mem_kind,
                                     uint64_t *ticket) {

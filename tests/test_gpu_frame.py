@@ -153,3 +153,24 @@ def test_frame_graph_replay_equals_launches(fm, monkeypatch):
         for k in ("depth", "normal", "conf"):
             assert np.array_equal(x[k], y[k]), (i, k)
     assert np.array_equal(runs["1"][0]["depth"], runs["1"][1]["depth"])
+
+
+def test_submit_with_one_depth_range_for_the_bundle(fm):
+    """fassmvs_submit_frame_range: the bundle's depth range applied to every
+    family without a distance range gives the maps of the same range given
+    per family."""
+    wl = scenegen.make_workload("config3_small_range")
+    h_, w_ = wl["height"], wl["width"]
+    fams = [dict(n=f["n"], delta_min=0.0, delta_max=0.0, count=f["count"]) for f in wl["families"]]
+    with fm.Handle(fm.config_from_params(wl["params"])) as h:
+        exp = h.run_frame(wl)
+        t = h.submit_frame_range(wl["ref"], wl["views"], wl["side"], wl["K"], 20.0, 400.0, fams)
+        d = np.zeros((h_, w_), np.float32)
+        n = np.zeros((h_, w_, 3), np.float32)
+        c = np.zeros((h_, w_), np.float32)
+        h.poll(t, d, n, c)
+        assert np.array_equal(d, exp["depth"]) and np.array_equal(n, exp["normal"]) and np.array_equal(c, exp["conf"])
+        for lo, hi in ((400.0, 20.0), (0.0, 10.0)):
+            with pytest.raises(fm.FassmvsError) as e:
+                h.submit_frame_range(wl["ref"], wl["views"], wl["side"], wl["K"], lo, hi, fams)
+            assert e.value.status == fm.EINVAL
