@@ -146,7 +146,9 @@ struct fassmvs_handle {
     struct BatchGraph {
         hipGraphExec_t exec = nullptr;
         uint64_t gen = 0;
+        uint64_t used = 0;   // last use (the least recently used graph is dropped when the cache is full)
     };
+    uint64_t graph_clock = 0;
     std::map<std::string, BatchGraph> graphs;
     std::map<std::string, BatchGraph> frame_graphs;   // single frames (profile off), by plan shape and values
     struct Tuning {
@@ -1154,6 +1156,22 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
 
 constexpr size_t kMaxFrameGraphs = 8;   // captured frame graphs kept per handle
 
+// The cache entry for key, making room (dropping the least recently used
+// graph) when the cache is full; marks it used.
+fassmvs_handle::BatchGraph &graph_slot(fassmvs_handle *h, std::map<std::string, fassmvs_handle::BatchGraph> &cache,
+                                       const std::string &key, size_t cap) {
+    if (cache.size() >= cap && !cache.count(key)) {
+        auto lru = cache.begin();
+        for (auto it = cache.begin(); it != cache.end(); ++it)
+            if (it->second.used < lru->second.used) lru = it;
+        if (lru->second.exec) hipGraphExecDestroy(lru->second.exec);
+        cache.erase(lru);
+    }
+    auto &g = cache[key];
+    g.used = ++h->graph_clock;
+    return g;
+}
+
 // A frame plan's shape and the values its launches take by value (the key
 // of a captured frame graph), with the launch-time tuning knobs.
 std::string plan_signature(const FramePlan &P) {
@@ -1201,12 +1219,7 @@ fassmvs_status enqueue_frame_graph(fassmvs_handle *h, const FramePlan &P) {
     const char *e = std::getenv("FASSMVS_FRAME_GRAPH");
     if (h->cfg.profile || (e && std::atoi(e) == 0)) return enqueue_frame(h, P);
     const std::string key = plan_signature(P);
-    if (h->frame_graphs.size() >= kMaxFrameGraphs && !h->frame_graphs.count(key)) {
-        for (auto &kv : h->frame_graphs)
-            if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-        h->frame_graphs.clear();
-    }
-    auto &g = h->frame_graphs[key];
+    auto &g = graph_slot(h, h->frame_graphs, key, kMaxFrameGraphs);
     if (!g.exec || g.gen != h->gen) {
         if (g.exec) hipGraphExecDestroy(g.exec);
         g.exec = nullptr;
@@ -1835,12 +1848,7 @@ fassmvs_status fassmvs_submit_batch(fassmvs_handle *h, const fassmvs_frame *fram
             uint64_t gen = h->gen;
             for (int i = 0; i < n_frames; ++i) gen += h->children[i]->gen;
             const std::string key = batch_signature(h, n_frames, &t, true);
-            if (h->graphs.size() >= kMaxBatchGraphs && !h->graphs.count(key)) {
-                for (auto &kv : h->graphs)
-                    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-                h->graphs.clear();
-            }
-            auto &g = h->graphs[key];
+            auto &g = graph_slot(h, h->graphs, key, kMaxBatchGraphs);
             if (!g.exec || g.gen != gen) {
                 if (g.exec) hipGraphExecDestroy(g.exec);
                 g.exec = nullptr;

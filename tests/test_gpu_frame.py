@@ -174,3 +174,23 @@ def test_submit_with_one_depth_range_for_the_bundle(fm):
             with pytest.raises(fm.FassmvsError) as e:
                 h.submit_frame_range(wl["ref"], wl["views"], wl["side"], wl["K"], lo, hi, fams)
             assert e.value.status == fm.EINVAL
+
+
+def test_frame_graph_cache_beyond_its_capacity(fm, monkeypatch):
+    """More frame shapes than the handle keeps graphs for (eight), revisited:
+    the least recently used graph is dropped and recaptured, maps unchanged."""
+    wl = scenegen.make_workload("config1")
+
+    def crop(w):
+        return dict(wl, width=w, ref=dict(wl["ref"], img=np.ascontiguousarray(wl["ref"]["img"][:, :w])),
+                    views=[dict(v, img=np.ascontiguousarray(v["img"][:, :w])) for v in wl["views"]])
+
+    shapes = [crop(160 - 8 * k) for k in range(10)] + [crop(160), crop(88)]
+    runs = {}
+    for graph in ("1", "0"):
+        monkeypatch.setenv("FASSMVS_FRAME_GRAPH", graph)
+        with fm.Handle(fm.config_from_params(wl["params"])) as h:
+            runs[graph] = [h.run_frame(x) for x in shapes]
+    for i, (x, y) in enumerate(zip(runs["1"], runs["0"])):
+        for k in ("depth", "normal", "conf"):
+            assert np.array_equal(x[k], y[k]), (i, k)
