@@ -140,6 +140,22 @@ def main():
             lines.append(f"| {k} | {fn[k]} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} | "
                          f"{ms if ms else float('nan'):.4f} | {gbs:.0f} |")
             traffic[k] = {"fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb}
+        # the summarised kernels by grid size (one row per distinct launch
+        # shape, e.g. per pyramid level)
+        by_grid = collections.defaultdict(lambda: [0.0, 0.0, 0])
+        for d, (name, grid, c) in fd.items():
+            if _base(name) in kernels and "FETCH_SIZE" in c:
+                by_grid[(name, grid)][0] += c["FETCH_SIZE"] * 1024.0 * ff
+                by_grid[(name, grid)][2] += 1
+        for d, (name, grid, c) in wd.items():
+            if _base(name) in kernels and "WRITE_SIZE" in c and (name, grid) in by_grid:
+                by_grid[(name, grid)][1] += c["WRITE_SIZE"] * 1024.0 * wf
+        if by_grid:
+            lines += ["", "By launch shape (grid size in work-items; the same shape is the same pyramid level):", "",
+                      "| kernel | grid | dispatches | fetch MB | write MB | total MB |", "|---|---|---|---|---|---|"]
+            for (name, grid), (fb, wb, n) in sorted(by_grid.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+                lines.append(f"| {name} | {grid} | {n} | {fb / n / 1e6:.1f} | {wb / n / 1e6:.1f} | "
+                             f"{(fb + wb) / n / 1e6:.1f} |")
 
     if a.sq:
         sd = read_counters(a.sq)

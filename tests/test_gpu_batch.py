@@ -190,3 +190,19 @@ def test_batch_errors(fm, frames):
         with pytest.raises(fm.FassmvsError) as e:
             h.submit_batch([wl, bad])
         assert e.value.status == fm.EINVAL
+
+
+def test_batch_with_device_inputs_and_outputs(fm, frames, alone):
+    """Device-resident images in and device maps out give the host path's
+    maps."""
+    sds = scenegen.CONFIG4_SEEDS[:5]
+    wls = [frames[sd] for sd in sds]
+    with fm.Handle(fm.config_from_params(wls[0]["params"])) as h:
+        dev = [dict(wl, ref=dict(wl["ref"], img=h.upload(wl["ref"]["img"])),
+                    views=[dict(v, img=h.upload(v["img"])) for v in wl["views"]]) for wl in wls]
+        t = h.submit_batch(dev, mem_kind=fm.MEM_DEVICE)
+        for i, (sd, wl) in enumerate(zip(sds, wls)):
+            d = h.empty((wl["height"], wl["width"]), np.float32)
+            c = h.empty((wl["height"], wl["width"]), np.float32)
+            h.poll_batch(t, i, d, None, c, mem_kind=fm.MEM_DEVICE)
+            assert np.array_equal(d.numpy(), alone[0][sd]["depth"]) and np.array_equal(c.numpy(), alone[0][sd]["conf"])
