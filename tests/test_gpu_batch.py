@@ -206,3 +206,26 @@ def test_batch_with_device_inputs_and_outputs(fm, frames, alone):
             c = h.empty((wl["height"], wl["width"]), np.float32)
             h.poll_batch(t, i, d, None, c, mem_kind=fm.MEM_DEVICE)
             assert np.array_equal(d.numpy(), alone[0][sd]["depth"]) and np.array_equal(c.numpy(), alone[0][sd]["conf"])
+
+
+def test_batch_of_the_most_frames(fm):
+    """64 frames (the most a batch takes) of 20 different widths: each equals
+    its run alone; 65 frames are refused."""
+    wl = scenegen.make_workload("config1")
+
+    def crop(w):
+        return dict(wl, width=w, ref=dict(wl["ref"], img=np.ascontiguousarray(wl["ref"]["img"][:, :w])),
+                    views=[dict(v, img=np.ascontiguousarray(v["img"][:, :w])) for v in wl["views"]])
+
+    shapes = [crop(160 - 4 * (i % 20)) for i in range(64)]
+    with fm.Handle(fm.config_from_params(wl["params"])) as h:
+        alone = {}
+        for x in shapes[:20]:
+            alone[x["width"]] = h.run_frame(x)
+        got = h.run_batch(shapes)
+        for x, g in zip(shapes, got):
+            for k in ("depth", "normal", "conf"):
+                assert np.array_equal(g[k], alone[x["width"]][k]), (x["width"], k)
+        with pytest.raises(fm.FassmvsError) as e:
+            h.submit_batch(shapes + shapes[:1])
+        assert e.value.status == fm.EINVAL
