@@ -10,10 +10,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# oracle runs the full-size parity tests compare with: (workload, last level
-# run or None for the whole frame), each in a process of its own, started as
-# soon as the session knows those tests are selected
-ORACLE_JOBS = {"config2": None, "config3": 2}
+# oracle runs the parity tests compare with: workload -> (last level run or
+# None for the whole frame, the test file that needs it), each in a process
+# of its own, started as soon as the session knows that file is selected
+ORACLE_JOBS = {"config2": (None, "test_gpu_fullsize"), "config3": (2, "test_gpu_fullsize"),
+               "config4_112": (None, "test_gpu_batch"), "config4_107": (None, "test_gpu_batch")}
 _jobs = {}
 
 
@@ -22,12 +23,15 @@ def pytest_configure(config):
 
 
 def pytest_collection_finish(session):
-    if not any("test_gpu_fullsize" in item.nodeid for item in session.items):
+    files = {f for _, f in ORACLE_JOBS.values() if any(f in item.nodeid for item in session.items)}
+    if not files:
         return
     import oracle
     oracle.build()
     tmp = tempfile.mkdtemp(prefix="fassmvs_oracle_")
-    for name, lv in ORACLE_JOBS.items():
+    for name, (lv, f) in ORACLE_JOBS.items():
+        if f not in files:
+            continue
         out = os.path.join(tmp, f"{name}.npz")
         cmd = [sys.executable, os.path.join(ROOT, "tests", "oracle_frame_job.py"), name, out]
         if lv is not None:

@@ -7,8 +7,8 @@ aggregation launch per level round, the whole batch replayed from a captured
 graph), every frame's maps are identical to the same frame run alone, on
 the graph's first capture, on its replay and without the graph; the same
 holds with sixteen handles in flight together.  The coarsest level of four
-frames (5 views in 3 + 2, 192 labels, 2 levels, 2 views) matches the oracle
-at the frame tests' gates."""
+frames (5 views in 3 + 2, 192 labels, 2 levels, 2 views) and every level of
+two more match the oracle at the frame tests' gates."""
 import copy
 import os
 import time
@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import scenegen
+from parity_util import compare_level
 
 pytestmark = pytest.mark.gpu
 
@@ -229,3 +230,25 @@ def test_batch_of_the_most_frames(fm):
         with pytest.raises(fm.FassmvsError) as e:
             h.submit_batch(shapes + shapes[:1])
         assert e.value.status == fm.EINVAL
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("sd", [112, 107])
+def test_batch_frame_every_level_matches_oracle(frames, alone, oracle_run, sd):
+    """Every level of two config4 frames (640x480: 2 views, 168 labels, 3
+    levels; 4 views, 184 labels, 2 levels) against the oracle's whole-frame
+    run (started in a process of its own when the session starts); the
+    batch gives these frames' maps bit for bit (above)."""
+    wl = frames[sd]
+    z = oracle_run(f"config4_{sd}")
+    h = alone[1][sd]
+    n = wl["params"]["n_levels"]
+    for l in range(n - 1, -1, -1):
+        got = dict(label=h.level_map(l, 4), depth=h.level_map(l, 0), normal=h.level_map(l, 2), conf=h.level_map(l, 3))
+        exp = dict(label=z[f"l{l}_label"], depth=z[f"l{l}_depth"], normal=z[f"l{l}_normal"], conf=z[f"l{l}_conf"])
+        rep = compare_level(got, exp, wl["params"]["normal_radius"])
+        print(f"[batch] config4_{sd} level {l}: {rep}", flush=True)
+        if l < n - 1:
+            nf = len(wl["families"])
+            assert np.mean(h.level_map(l, 6, n_fam=nf) == z[f"l{l}_offs"]) >= 0.999
+            assert np.mean(h.level_map(l, 7, n_fam=nf) == z[f"l{l}_dI"]) >= 0.999
