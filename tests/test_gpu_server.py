@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import scenegen
+from parity_util import compare_level
 
 pytestmark = pytest.mark.gpu
 
@@ -79,7 +80,10 @@ def test_same_alone_and_in_the_mix(fm, streams):
     assert alone[(0, 0)][0]["status"] == fm.ENOTFOUND
 
 
-def test_served_frame_equals_plain_pipeline(fm, streams):
+def test_served_frame_equals_plain_pipeline(fm, orc, streams):
+    """A served frame's maps equal the plain pipeline's on the same bundle
+    (the frame and the keyframes it was matched against), and that bundle's
+    maps match the oracle's at every level."""
     st = streams[0]
     cfg = _cfg(fm, st)
     served = _run(fm, [st], [(0, f) for f in range(4)], 2, cfg)
@@ -95,12 +99,19 @@ def test_served_frame_equals_plain_pipeline(fm, streams):
     img, R, t = st["frames"][3]
     ref = dict(img=img, R=R, t=t)
     views = [dict(img=st["frames"][k][0], R=st["frames"][k][1], t=st["frames"][k][2]) for k in kf]
-    with fm.Handle(cfg) as h:
+    wl = dict(K=st["K"], width=st["width"], height=st["height"], ref=ref, views=views, side=[-1] * len(kf),
+              families=st["families"], params=st["params"])
+    oref = orc.run_frame(wl, keep=True)
+    with fm.Handle(fm.config_from_params(st["params"], keep_levels=1)) as h:
         tk = h.submit_frame(ref, views, [-1] * len(kf), st["K"], st["families"])
         d = np.zeros((st["height"], st["width"]), np.float32)
         n = np.zeros((st["height"], st["width"], 3), np.float32)
         c = np.zeros((st["height"], st["width"]), np.float32)
         h.poll(tk, d, n, c)
+        for l in range(st["params"]["n_levels"]):
+            got = dict(label=h.level_map(l, 4), depth=h.level_map(l, 0), normal=h.level_map(l, 2),
+                       conf=h.level_map(l, 3))
+            compare_level(got, oref["levels"][l], st["params"]["normal_radius"])
     maps = served[(0, 3)][1]
     assert np.array_equal(maps["depth"], d)
     assert np.array_equal(maps["normal"], n)
