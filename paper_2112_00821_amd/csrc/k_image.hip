@@ -248,11 +248,8 @@ __global__ __launch_bounds__(256) void k_smooth_conf(const NormalArgs a) {
     o[0] = o[1] = o[2] = 0.0f;
     a.conf[p] = 0.0f;
     if (np_[0] == 0.0f && np_[1] == 0.0f && np_[2] == 0.0f) return;
-    const double PI = 3.14159265358979323846;
-    double sigma = (double)a.radius;
-    double g0 = 1.0 / sqrt(2.0 * PI * sigma * sigma);
     double acc[3] = {np_[0], np_[1], np_[2]};
-    double Ip = (double)a.img[p];
+    const int Ip = a.img[p];
     for (int dy = -a.radius; dy <= a.radius; ++dy)
         for (int dx = -a.radius; dx <= a.radius; ++dx) {
             if (dx == 0 && dy == 0) continue;
@@ -260,8 +257,9 @@ __global__ __launch_bounds__(256) void k_smooth_conf(const NormalArgs a) {
             if (xx < 0 || xx >= a.w || yy < 0 || yy >= a.h) continue;
             size_t q = (size_t)yy * a.w + xx;
             const float *nq = a.nraw + 3 * q;
-            double dI = fabs(Ip - (double)a.img[q]);
-            double wq = g0 * exp(-(double)(dx * dx + dy * dy) / (2.0 * sigma * sigma) - dI / a.beta);
+            // the weight of Eq. normal-smooth for this offset and intensity
+            // difference, from the table
+            const double wq = a.wtab[(dx * dx + dy * dy) * 256 + abs(Ip - (int)a.img[q])];
             acc[0] += wq * nq[0];
             acc[1] += wq * nq[1];
             acc[2] += wq * nq[2];

@@ -112,6 +112,10 @@ hipError_t launch_median5(const float *in, int w, int h, float *out, hipStream_t
 struct NormalArgs {
     int w, h, radius;
     double beta, cos_rho;
+    // smoothing weights g0 exp(-d2 / (2 sigma^2) - dI / beta) by squared
+    // offset d2 (0..2 radius^2) and intensity difference dI (0..255):
+    // [d2][256], computed on the host (device memory)
+    const double *wtab;
     double Kinv[9];
     int n_fam;
     double fam_n[kMaxFam][3];

@@ -182,6 +182,9 @@ struct fassmvs_handle {
     int32_t stage_n_lv[FASSMVS_MAX_LEVELS][ST_COUNT] = {};
     int cur_level = -1;                 // level the timers being enqueued belong to (-1: frame-wide)
     bool prebuilt = false;              // this frame's device images carry their whole pyramids
+    DevBuf wtab;                        // normal-smoothing weight table (see weight_table)
+    int wtab_radius = -1;
+    double wtab_beta = 0.0;
     hipEvent_t frame_t0 = nullptr;      // the frame's start on the stream (profiling)
     std::vector<fassmvs_timeline_entry> timeline;   // the last polled frame's timed steps
     double last_work[4] = {};
@@ -747,6 +750,32 @@ size_t pyr_total(int w, int hh, int levels) {
 }
 
 // Every device buffer a frame needs and its size in bytes.
+// The normal-smoothing weights of Eq. normal-smooth, g0 exp(-d2 / (2
+// sigma^2) - dI / beta) with sigma = radius and g0 = 1 / sqrt(2 pi sigma^2),
+// for every squared offset d2 = 0..2 radius^2 and intensity difference
+// dI = 0..255, evaluated on the host in double (the expression as written),
+// uploaded to the handle's table once per (radius, beta).  Synchronous: call
+// outside graph capture.
+fassmvs_status weight_table(fassmvs_handle *h, int radius, double beta) {
+    if (h->wtab.p && h->wtab_radius == radius && h->wtab_beta == beta) return FASSMVS_OK;
+    const double PI = 3.14159265358979323846;
+    const double sigma = (double)radius;
+    const double g0 = 1.0 / std::sqrt(2.0 * PI * sigma * sigma);
+    const int nd = 2 * radius * radius + 1;
+    std::vector<double> t((size_t)nd * 256);
+    for (int d2 = 0; d2 < nd; ++d2)
+        for (int i = 0; i < 256; ++i) {
+            const double dI = (double)i;
+            t[(size_t)d2 * 256 + i] = g0 * std::exp(-(double)d2 / (2.0 * sigma * sigma) - dI / beta);
+        }
+    fassmvs_status st = ensure(h, h->wtab, t.size() * 8);
+    if (st != FASSMVS_OK) return st;
+    HIPCHK(h, hipMemcpy(h->wtab.p, t.data(), t.size() * 8, hipMemcpyHostToDevice), "weight table");
+    h->wtab_radius = radius;
+    h->wtab_beta = beta;
+    return FASSMVS_OK;
+}
+
 void frame_buffers(fassmvs_handle *h, const FramePlan &P, std::vector<std::pair<DevBuf *, size_t>> &out) {
     const fassmvs_config &c = h->cfg;
     const size_t N0 = (size_t)P.w * P.h;
@@ -1046,6 +1075,7 @@ fassmvs_status enqueue_post(fassmvs_handle *h, const FramePlan &P, int l) {
         a.h = L.h;
         a.radius = c.normal_radius;
         a.beta = c.normal_beta;
+        a.wtab = (const double *)h->wtab.p;
         a.cos_rho = std::cos(c.conf_rho_deg * 3.14159265358979323846 / 180.0);
         std::memcpy(a.Kinv, L.Kinv, sizeof(a.Kinv));
         a.n_fam = L.F;
@@ -1104,6 +1134,8 @@ fassmvs_status enqueue_post(fassmvs_handle *h, const FramePlan &P, int l) {
 // through the handle's pinned staging (host images) or device copies.
 fassmvs_status upload_frame(fassmvs_handle *h, const FramePlan &P, const fassmvs_image *ref,
                             const fassmvs_image *views, int mem_kind) {
+    fassmvs_status wst = weight_table(h, h->cfg.normal_radius, h->cfg.normal_beta);
+    if (wst != FASSMVS_OK) return wst;
     const size_t N0 = (size_t)P.w * P.h;
     Timer t(h, ST_UPLOAD);
     uint8_t *pin = (uint8_t *)h->pin;
@@ -2162,6 +2194,7 @@ void fassmvs_destroy(fassmvs_handle *h) {
         release(h->params);
         release(h->work_ctr);
         release(h->sbar);
+        release(h->wtab);
         for (auto &b : h->sgmbuf) release(b);
         for (auto &L : h->lb) {
             release(L.depth_raw); release(L.depth); release(L.nraw); release(L.normal); release(L.conf);
@@ -2717,8 +2750,11 @@ fassmvs_status fassmvs_stage_normals(fassmvs_handle *h, const float *depth, cons
     std::memset(&a, 0, sizeof(a));
     a.w = w;
     a.h = hgt;
+    fassmvs_status wst = weight_table(h, radius, beta);
+    if (wst != FASSMVS_OK) return wst;
     a.radius = radius;
     a.beta = beta;
+    a.wtab = (const double *)h->wtab.p;
     a.cos_rho = std::cos(rho_deg * 3.14159265358979323846 / 180.0);
     std::memcpy(a.Kinv, Kinv, 72);
     a.n_fam = n_fam;

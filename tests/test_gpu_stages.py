@@ -2,10 +2,11 @@
 
 Integer stages (pyramid, census, cost volume, path costs, aggregate, WTA,
 window offsets, surface-normal offsets, median) must be bit-exact; the warp
-is held to |diff| <= 1e-4 on the [0, 1] scale (and is bit-exact in practice
-because coordinates are computed in double on both sides); refined depth to
-1e-6 relative (double arithmetic on both sides), normals and confidence to
-float rounding (1e-5).  Every call goes through the C ABI."""
+is held to |diff| <= 1e-4 on the [0, 1] scale (and is bit-exact in practice:
+coordinates are computed in double on both sides, the kernel's reciprocal
+within an ulp of the oracle's); refined depth to 1e-6 relative (double
+arithmetic on both sides); normals, smoothed normals and confidence
+bit-exact.  Every call goes through the C ABI."""
 import numpy as np
 import pytest
 
@@ -211,9 +212,12 @@ def test_refine_median_normals_conf(orc, hd):
     assert np.array_equal(med, lv["depth"])
     nraw, normal, conf = hd.stage_normals(hd.upload(lv["depth"]), hd.upload(lv["img"]), Ki, 2, 10.0,
                                           hd.upload(lv["label"]), hd.upload(lv["fam"]), plan["fam_n"], 60.0)
-    assert np.max(np.abs(nraw.numpy() - lv["normal_raw"])) <= 1e-6
-    assert np.max(np.abs(normal.numpy() - lv["normal"])) <= 1e-5
-    assert np.max(np.abs(conf.numpy() - lv["conf"])) <= 1e-5
+    # the smoothing weights come from a table the host evaluates with the
+    # oracle's expression and libm, so the smoothed normals and the
+    # confidence are the oracle's floats
+    assert np.array_equal(nraw.numpy(), lv["normal_raw"]), first_mismatch(nraw.numpy(), lv["normal_raw"])
+    assert np.array_equal(normal.numpy(), lv["normal"]), first_mismatch(normal.numpy(), lv["normal"])
+    assert np.array_equal(conf.numpy(), lv["conf"]), first_mismatch(conf.numpy(), lv["conf"])
 
 
 def test_seed_bit_exact(orc, hd):
