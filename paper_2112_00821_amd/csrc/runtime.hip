@@ -183,6 +183,7 @@ struct fassmvs_handle {
     int cur_level = -1;                 // level the timers being enqueued belong to (-1: frame-wide)
     bool prebuilt = false;              // this frame's device images carry their whole pyramids
     DevBuf wtab;                        // normal-smoothing weight table (see weight_table)
+    const void *wtab_at = nullptr;      // the allocation the table was last written to
     int wtab_radius = -1;
     double wtab_beta = 0.0;
     hipEvent_t frame_t0 = nullptr;      // the frame's start on the stream (profiling)
@@ -749,15 +750,17 @@ size_t pyr_total(int w, int hh, int levels) {
     return s;
 }
 
-// Every device buffer a frame needs and its size in bytes.
 // The normal-smoothing weights of Eq. normal-smooth, g0 exp(-d2 / (2
 // sigma^2) - dI / beta) with sigma = radius and g0 = 1 / sqrt(2 pi sigma^2),
 // for every squared offset d2 = 0..2 radius^2 and intensity difference
 // dI = 0..255, evaluated on the host in double (the expression as written),
 // uploaded to the handle's table once per (radius, beta).  Synchronous: call
 // outside graph capture.
+size_t weight_table_bytes(int radius) { return (size_t)(2 * radius * radius + 1) * 256 * 8; }
+
 fassmvs_status weight_table(fassmvs_handle *h, int radius, double beta) {
-    if (h->wtab.p && h->wtab_radius == radius && h->wtab_beta == beta) return FASSMVS_OK;
+    if (h->wtab.p && h->wtab.p == h->wtab_at && h->wtab_radius == radius && h->wtab_beta == beta)
+        return FASSMVS_OK;
     const double PI = 3.14159265358979323846;
     const double sigma = (double)radius;
     const double g0 = 1.0 / std::sqrt(2.0 * PI * sigma * sigma);
@@ -771,11 +774,13 @@ fassmvs_status weight_table(fassmvs_handle *h, int radius, double beta) {
     fassmvs_status st = ensure(h, h->wtab, t.size() * 8);
     if (st != FASSMVS_OK) return st;
     HIPCHK(h, hipMemcpy(h->wtab.p, t.data(), t.size() * 8, hipMemcpyHostToDevice), "weight table");
+    h->wtab_at = h->wtab.p;
     h->wtab_radius = radius;
     h->wtab_beta = beta;
     return FASSMVS_OK;
 }
 
+// Every device buffer a frame needs and its size in bytes.
 void frame_buffers(fassmvs_handle *h, const FramePlan &P, std::vector<std::pair<DevBuf *, size_t>> &out) {
     const fassmvs_config &c = h->cfg;
     const size_t N0 = (size_t)P.w * P.h;
@@ -795,6 +800,7 @@ void frame_buffers(fassmvs_handle *h, const FramePlan &P, std::vector<std::pair<
         out.emplace_back(&h->post_m1, N0);
     }
     out.emplace_back(&h->c3, N0 * 6);
+    out.emplace_back(&h->wtab, weight_table_bytes(c.normal_radius));
     out.emplace_back(&h->params, P.blob.size() * 8);
     out.emplace_back(&h->work_ctr, 8);
     for (int l = 0; l < P.n_levels; ++l) {
@@ -1669,7 +1675,7 @@ fassmvs_status fassmvs_frame_footprint(const fassmvs_config *cfg, int32_t w, int
     }
     const size_t N0 = (size_t)w * hgt;
     size_t total = NDmax * (1 + 2 * (size_t)cfg->n_paths) + maps + pyr_total(w, hgt, cfg->n_levels) * (n_views + 1) +
-                   N0 * (8 + 2 + 6) + params + 256;
+                   N0 * (8 + 2 + 6) + params + weight_table_bytes(cfg->normal_radius) + 256;
     if (cfg->sgm_debug) total += NDmax * 2;
     if (cfg->dog_filter) total += N0 * 10;
     *bytes = total;
