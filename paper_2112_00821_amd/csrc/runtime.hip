@@ -989,7 +989,16 @@ SweepArgs sweep_args(fassmvs_handle *h, const FramePlan &P, int l) {
     a.offs = L.windows ? (const int32_t *)h->lb[l].offs.p : nullptr;
     a.S = (uint8_t *)h->S.p;
     a.work = (unsigned long long *)h->work_ctr.p;
-    a.rows_per_thread = sweep_rows();
+    // Tile height for the census cost (FASSMVS_SWEEP_ROWS overrides): 64x16
+    // tiles where several plane families share the level (each family's
+    // label windows move across a tile, and a shorter tile evaluates a
+    // smaller union of them; it also keeps 4 waves per SIMD resident) or
+    // where the level is small (more tiles to spread over the CUs); 64x32
+    // otherwise (less halo to warp).  The same costs either way.
+    int rows = sweep_rows();
+    if (rows == 0 && c.cost == 0)
+        rows = (L.F > 1 || (double)L.w * L.h * L.D <= 33554432.0) ? 4 : 8;
+    a.rows_per_thread = rows;
     return a;
 }
 
