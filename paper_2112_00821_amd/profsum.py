@@ -121,7 +121,7 @@ def main():
         ff, fcal_raw = calibration(fd, "FETCH_SIZE", copy_bytes)
         wf, wcal_raw = calibration(wd, "WRITE_SIZE", copy_bytes)
         favg, fn = per_kernel_avg(fd, "FETCH_SIZE")
-        wavg, _ = per_kernel_avg(wd, "WRITE_SIZE")
+        wavg, wn = per_kernel_avg(wd, "WRITE_SIZE")
         avg_ms = {}
         for n, calls, avg, tot, pct in stats:
             avg_ms[n] = avg
@@ -139,7 +139,8 @@ def main():
             gbs = (fb + wb) / (ms / 1e3) / 1e9 if ms else float("nan")
             lines.append(f"| {k} | {fn[k]} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} | "
                          f"{ms if ms else float('nan'):.4f} | {gbs:.0f} |")
-            traffic[k] = {"fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb}
+            traffic[k] = {"fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb, "fetch_n": fn[k],
+                          "write_n": wn.get(k, 0)}
         # the summarised kernels by grid size (one row per distinct launch
         # shape, e.g. per pyramid level)
         by_grid = collections.defaultdict(lambda: [0.0, 0.0, 0])
@@ -184,13 +185,19 @@ def main():
 
     recs = []
     for kern in kernels:
-        # the instantiation with the most traffic stands for the kernel
-        dom = sorted((k for k in traffic if _base(k) == kern), key=lambda k: -traffic[k]["bytes"])
-        if dom:
-            recs.append({"kernel": kern, "instantiation": dom[0], "source_hash": source_hash(kern),
-                         "traffic_bytes_per_launch": traffic[dom[0]]["bytes"],
-                         "fetch_bytes_per_launch": traffic[dom[0]]["fetch_bytes"],
-                         "write_bytes_per_launch": traffic[dom[0]]["write_bytes"]})
+        # per launch over every instantiation of the kernel (the frame's
+        # launches may use several, e.g. one tile height per level), as the
+        # benchmark averages its launch times; the instantiation with the
+        # most traffic is named
+        inst = sorted((k for k in traffic if _base(k) == kern), key=lambda k: -traffic[k]["bytes"])
+        nf = sum(traffic[k]["fetch_n"] for k in inst)
+        nw = sum(traffic[k]["write_n"] for k in inst)
+        if inst and nf and nw:
+            fetch = sum(traffic[k]["fetch_bytes"] * traffic[k]["fetch_n"] for k in inst) / nf
+            write = sum(traffic[k]["write_bytes"] * traffic[k]["write_n"] for k in inst) / nw
+            recs.append({"kernel": kern, "instantiation": inst[0], "instantiations": inst,
+                         "source_hash": source_hash(kern), "traffic_bytes_per_launch": fetch + write,
+                         "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write})
     if recs:
         lines += ["", "## Traffic records read by bench.py", ""]
         lines += ["traffic_json: " + json.dumps(r) for r in recs]

@@ -72,3 +72,33 @@ def test_counters_scaled_by_the_copy_kernel(tmp_path):
     assert rec["instantiation"] == "k_sweep<9, 7, 8, false, 0>"
     txt = out.read_text()
     assert "factors 2.0000 (fetch) and 1.0000 (write)" in txt
+
+
+def test_traffic_record_averages_over_instantiations(tmp_path):
+    """A frame's launches of one kernel may use several instantiations (a
+    tile height per level): the record is per launch over all of them."""
+    mb = 4
+    copy_bytes = mb << 20
+    hdr = ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"]
+    k8 = "void fmvs::k_sweep<9, 7, 8, false, 0>(fmvs::SweepArgs)"
+    k4 = "void fmvs::k_sweep<9, 7, 4, false, 0>(fmvs::SweepArgs)"
+    for counter, copy_kib, vals in (("FETCH_SIZE", copy_bytes / 2 / 1024, (600.0, 300.0, 30.0)),
+                                    ("WRITE_SIZE", copy_bytes / 1024, (900.0, 450.0, 60.0))):
+        d = tmp_path / counter
+        os.makedirs(d)
+        rows = [[1, "void fmvs::k_copy16(uint4 const*, uint4*, unsigned long)", 1024, counter, copy_kib],
+                [2, k8, 4096, counter, vals[0]], [3, k8, 2048, counter, vals[1]], [4, k4, 1024, counter, vals[2]]]
+        _write(os.path.join(d, "run_counter_collection.csv"), hdr, rows)
+    os.makedirs(tmp_path / "trace")
+    _write(tmp_path / "trace" / "run_kernel_stats.csv", ["Name", "Calls", "AverageNs", "TotalDurationNs", "Percentage"],
+           [[k8, 2, 2.0e6, 4.0e6, 90.0], [k4, 1, 0.4e6, 0.4e6, 10.0]])
+    out = tmp_path / "p.md"
+    subprocess.run([sys.executable, "-m", "paper_2112_00821_amd.profsum", "--trace", str(tmp_path / "trace"),
+                    "--fetch", str(tmp_path / "FETCH_SIZE"), "--write", str(tmp_path / "WRITE_SIZE"),
+                    "--copy-mb", str(mb), "--kernel", "k_sweep", "--workload", "synthetic", "--out", str(out)],
+                   check=True, cwd=ROOT)
+    rec = profsum.read_traffic(str(out), "k_sweep")
+    assert rec["fetch_bytes_per_launch"] == pytest.approx((600 + 300 + 30) / 3 * 1024 * 2.0)
+    assert rec["write_bytes_per_launch"] == pytest.approx((900 + 450 + 60) / 3 * 1024 * 1.0)
+    assert rec["instantiation"] == "k_sweep<9, 7, 8, false, 0>"
+    assert sorted(rec["instantiations"]) == ["k_sweep<9, 7, 4, false, 0>", "k_sweep<9, 7, 8, false, 0>"]
