@@ -225,7 +225,8 @@ fassmvs_status fassmvs_poll_batch(fassmvs_handle *h, uint64_t ticket, int32_t in
                                   float *confidence, int32_t mem_kind, int32_t wait_ms);
 
 /* What the batch tuner chose for the last batch shape: sweep rows per
- * thread (tile height / 4), sweep workgroup target, number of frame groups
+ * thread (tile height / 4; 0: each frame level's own choice, as a single
+ * frame would take it), sweep workgroup target, number of frame groups
  * (each on a stream of its own), whether the batch replays a captured graph
  * (1) or is launched call by call (0), and the measured time of one batch
  * in ms.  Any output may be NULL. */

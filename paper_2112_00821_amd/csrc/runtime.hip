@@ -152,7 +152,7 @@ struct fassmvs_handle {
     std::map<std::string, BatchGraph> graphs;
     std::map<std::string, BatchGraph> frame_graphs;   // single frames (profile off), by plan shape and values
     struct Tuning {
-        int rpt = 8, target = 8192, groups = 1;
+        int rpt = 0, target = 8192, groups = 1;   // rpt 0: each frame level's own tile height
         bool graph = true;
         double ms = 0.0;
     };
@@ -1312,10 +1312,16 @@ struct SgmLaunch {
     bool win = false, sn = false;
 };
 
+// One sweep launch over some frames of a round (one tile height).
+struct SweepLaunch {
+    size_t off = 0;
+    int rpt = 8, blocks = 0;
+    std::vector<int> idx;   // positions in the round's frame list
+};
+
 struct BatchRound {
     std::vector<int> frames, levels;   // frames (batch order) and their level in this round
-    size_t sweep_off = 0;
-    int sweep_blocks = 0;
+    std::vector<SweepLaunch> sweeps;   // one per tile height among the round's frames
     std::vector<SgmLaunch> sgm;
     std::vector<char> own_sgm;   // per frame of the round: aggregates in launches of its own
 };
@@ -1324,12 +1330,19 @@ struct BatchGroup {
     std::vector<int> frames;
     std::vector<BatchRound> rounds;
     size_t counter_off = 0;   // the persistent aggregation's job counter
-    int rpt = 8;              // sweep rows per thread
 };
+
+// Sweep rows per thread of a frame level in a batch: the tuned value, or
+// with 0 the level's own choice (sweep_args), as a single frame would run.
+int batch_rows(fassmvs_handle *c, int l, int tuned) {
+    if (tuned == 4 || tuned == 8) return tuned;
+    const int r = sweep_args(c, c->plan, l).rows_per_thread;
+    return (r == 4 || r == 8) ? r : (c->cfg.cost == 1 ? 4 : 8);
+}
 
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxBatchGraphs = 8;   // captured batch graphs kept per handle
-constexpr int kMaxBatchGroups = 8;
+constexpr int kMaxBatchGroups = 16;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // The batch's shape: sizes, view split, plane counts and windows of every
@@ -1400,7 +1413,6 @@ fassmvs_status batch_prepare(fassmvs_handle *h, int n, const fassmvs_handle::Tun
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         BatchGroup &g = groups[gi];
         g.frames = assign[gi];
-        g.rpt = t.rpt;
         int R = 0;
         for (int i : g.frames) R = std::max(R, h->children[i]->plan.n_levels);
         g.rounds.assign(R, BatchRound());
@@ -1412,8 +1424,16 @@ fassmvs_status batch_prepare(fassmvs_handle *h, int n, const fassmvs_handle::Tun
                 br.frames.push_back(i);
                 br.levels.push_back(l);
             }
-            br.sweep_off = off;
-            off = align_up(off + sweep_batch_bytes((int)br.frames.size()));
+            for (int rpt : {8, 4}) {
+                SweepLaunch S;
+                S.rpt = rpt;
+                for (size_t j = 0; j < br.frames.size(); ++j)
+                    if (batch_rows(h->children[br.frames[j]], br.levels[j], t.rpt) == rpt) S.idx.push_back((int)j);
+                if (S.idx.empty()) continue;
+                S.off = off;
+                off = align_up(off + sweep_batch_bytes((int)S.idx.size()));
+                br.sweeps.push_back(S);
+            }
             int count[5] = {0, 0, 0, 0, 0};
             for (size_t j = 0; j < br.frames.size(); ++j) {
                 const int D = h->children[br.frames[j]]->plan.lv[br.levels[j]].D;
@@ -1452,13 +1472,15 @@ fassmvs_status batch_prepare(fassmvs_handle *h, int n, const fassmvs_handle::Tun
     for (auto &g : groups)
         for (auto &br : g.rounds) {
             const int m = (int)br.frames.size();
-            std::vector<SweepArgs> sw(m);
-            for (int j = 0; j < m; ++j) {
-                fassmvs_handle *c = h->children[br.frames[j]];
-                sw[j] = sweep_args(c, c->plan, br.levels[j]);
+            for (auto &S : br.sweeps) {
+                std::vector<SweepArgs> sw;
+                for (int j : S.idx) {
+                    fassmvs_handle *c = h->children[br.frames[j]];
+                    sw.push_back(sweep_args(c, c->plan, br.levels[j]));
+                }
+                S.blocks = prepare_sweep_batch(sw.data(), (int)sw.size(), S.rpt, t.target, stage + S.off);
+                if (S.blocks < 0) return fail(h, FASSMVS_EINVAL, "frames of a batch must share the matching cost");
             }
-            br.sweep_blocks = prepare_sweep_batch(sw.data(), m, t.rpt, t.target, stage + br.sweep_off);
-            if (br.sweep_blocks < 0) return fail(h, FASSMVS_EINVAL, "frames of a batch must share the matching cost");
             br.own_sgm.assign(m, shared_sgm ? 0 : 1);
             for (auto &L : br.sgm) {
                 std::vector<SgmArgs> sg;
@@ -1498,8 +1520,11 @@ fassmvs_status batch_enqueue_group(fassmvs_handle *h, const BatchGroup &g, hipSt
             fassmvs_handle *ch = h->children[br.frames[j]];
             if ((st = enqueue_census(ch, ch->plan, br.levels[j])) != FASSMVS_OK) return fail(h, st, ch->err);
         }
-        HIPCHK(h, launch_sweep_batch(dev + br.sweep_off, m, br.sweep_blocks, g.rpt, c.census_w, c.census_h, c.cost, s),
-               "batched sweep launch");
+        for (const SweepLaunch &S : br.sweeps)
+            HIPCHK(h,
+                   launch_sweep_batch(dev + S.off, (int)S.idx.size(), S.blocks, S.rpt, c.census_w, c.census_h, c.cost,
+                                      s),
+                   "batched sweep launch");
         for (const SgmLaunch &L : br.sgm)
             if (L.jobs >= 0)
                 HIPCHK(h, launch_sgm_batch(dev + L.off, L.n, L.jobs, L.kp, L.win, L.sn, L.nf, counter, s),
@@ -1963,11 +1988,11 @@ fassmvs_status fassmvs_submit_batch(fassmvs_handle *h, const fassmvs_frame *fram
             return s2;
         };
         for (int G = 1; G <= std::min(n_frames, kMaxBatchGroups); G *= 2)
-            if ((st = trial(8, 8192, G)) != FASSMVS_OK) return st;
+            if ((st = trial(0, 8192, G)) != FASSMVS_OK) return st;
         const int G = best.groups;
-        for (int rpt : {8, 4})
+        for (int rpt : {0, 8, 4})
             for (int target : {8192, 16384})
-                if (!(rpt == 8 && target == 8192) && (st = trial(rpt, target, G)) != FASSMVS_OK) return st;
+                if (!(rpt == 0 && target == 8192) && (st = trial(rpt, target, G)) != FASSMVS_OK) return st;
         if (graph_on) {
             // launched call by call instead, if that is faster
             double e = 0.0;
