@@ -145,6 +145,7 @@ struct fassmvs_handle {
     size_t batch_stage_bytes = 0;
     struct BatchGraph {
         hipGraphExec_t exec = nullptr;
+        std::vector<hipGraphExec_t> parts;   // a batch: one graph per frame group
         uint64_t gen = 0;
         uint64_t used = 0;   // last use (the least recently used graph is dropped when the cache is full)
     };
@@ -1203,6 +1204,14 @@ fassmvs_status enqueue_frame(fassmvs_handle *h, const FramePlan &P) {
 
 constexpr size_t kMaxFrameGraphs = 8;   // captured frame graphs kept per handle
 
+void release_graph(fassmvs_handle::BatchGraph &g) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    for (hipGraphExec_t e : g.parts)
+        if (e) hipGraphExecDestroy(e);
+    g.parts.clear();
+}
+
 // The cache entry for key, making room (dropping the least recently used
 // graph) when the cache is full; marks it used.
 fassmvs_handle::BatchGraph &graph_slot(fassmvs_handle *h, std::map<std::string, fassmvs_handle::BatchGraph> &cache,
@@ -1211,7 +1220,7 @@ fassmvs_handle::BatchGraph &graph_slot(fassmvs_handle *h, std::map<std::string, 
         auto lru = cache.begin();
         for (auto it = cache.begin(); it != cache.end(); ++it)
             if (it->second.used < lru->second.used) lru = it;
-        if (lru->second.exec) hipGraphExecDestroy(lru->second.exec);
+        release_graph(lru->second);
         cache.erase(lru);
     }
     auto &g = cache[key];
@@ -1268,8 +1277,7 @@ fassmvs_status enqueue_frame_graph(fassmvs_handle *h, const FramePlan &P) {
     const std::string key = plan_signature(P);
     auto &g = graph_slot(h, h->frame_graphs, key, kMaxFrameGraphs);
     if (!g.exec || g.gen != h->gen) {
-        if (g.exec) hipGraphExecDestroy(g.exec);
-        g.exec = nullptr;
+        release_graph(g);
         HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed), "frame graph capture");
         fassmvs_status st = enqueue_frame(h, P);
         hipGraph_t graph = nullptr;
@@ -1921,28 +1929,44 @@ fassmvs_status fassmvs_submit_batch(fassmvs_handle *h, const fassmvs_frame *fram
             for (int i = 0; i < n_frames; ++i) gen += h->children[i]->gen;
             const std::string key = batch_signature(h, n_frames, &t, true);
             auto &g = graph_slot(h, h->graphs, key, kMaxBatchGraphs);
-            if (!g.exec || g.gen != gen) {
-                if (g.exec) hipGraphExecDestroy(g.exec);
-                g.exec = nullptr;
-                // the launches of the whole batch, captured once and replayed
-                // while the shape and the buffers stay
-                HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed), "graph capture");
-                s2 = batch_enqueue(h, groups, nullptr);
-                hipGraph_t graph_ = nullptr;
-                hipError_t e = hipStreamEndCapture(h->stream, &graph_);
-                if (s2 != FASSMVS_OK) {
+            const size_t G = groups.size();
+            if (g.parts.size() != G || g.gen != gen) {
+                release_graph(g);
+                // each group's launches captured once on its stream and
+                // replayed while the shape and the buffers stay: the groups'
+                // graphs launch one after another, so the first group runs
+                // while the host launches the rest
+                g.parts.assign(G, nullptr);
+                for (size_t gi = 0; gi < G; ++gi) {
+                    hipStream_t gs = G == 1 ? h->stream : h->group_streams[gi];
+                    HIPCHK(h, hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed), "graph capture");
+                    s2 = batch_enqueue_group(h, groups[gi], gs);
+                    hipGraph_t graph_ = nullptr;
+                    hipError_t e = hipStreamEndCapture(gs, &graph_);
+                    if (s2 == FASSMVS_OK && e == hipSuccess)
+                        e = hipGraphInstantiate(&g.parts[gi], graph_, nullptr, nullptr, 0);
                     if (graph_) hipGraphDestroy(graph_);
-                    h->graphs.erase(key);
-                    return s2;
+                    if (s2 != FASSMVS_OK || e != hipSuccess) {
+                        release_graph(g);
+                        h->graphs.erase(key);
+                        if (s2 != FASSMVS_OK) return s2;
+                        HIPCHK(h, e, "graph capture");
+                    }
                 }
-                HIPCHK(h, e, "graph capture");
-                e = hipGraphInstantiate(&g.exec, graph_, nullptr, nullptr, 0);
-                hipGraphDestroy(graph_);
-                HIPCHK(h, e, "graph instantiation");
                 g.gen = gen;
             }
             if (ev) HIPCHK(h, hipEventRecord(ev[0], h->stream), "timing event");
-            HIPCHK(h, hipGraphLaunch(g.exec, h->stream), "graph launch");
+            if (G == 1) {
+                HIPCHK(h, hipGraphLaunch(g.parts[0], h->stream), "graph launch");
+            } else {
+                HIPCHK(h, hipEventRecord(h->group_ev[0], h->stream), "batch fork");
+                for (size_t gi = 0; gi < G; ++gi) {
+                    HIPCHK(h, hipStreamWaitEvent(h->group_streams[gi], h->group_ev[0], 0), "batch fork");
+                    HIPCHK(h, hipGraphLaunch(g.parts[gi], h->group_streams[gi]), "graph launch");
+                    HIPCHK(h, hipEventRecord(h->group_ev[gi + 1], h->group_streams[gi]), "batch join");
+                    HIPCHK(h, hipStreamWaitEvent(h->stream, h->group_ev[gi + 1], 0), "batch join");
+                }
+            }
             if (ev) HIPCHK(h, hipEventRecord(ev[1], h->stream), "timing event");
         } else if ((s2 = batch_enqueue(h, groups, ev)) != FASSMVS_OK) {
             return s2;
@@ -2240,10 +2264,8 @@ void fassmvs_destroy(fassmvs_handle *h) {
             release(L.depth_raw); release(L.depth); release(L.nraw); release(L.normal); release(L.conf);
             release(L.label); release(L.fam); release(L.offs); release(L.dI); release(L.dbar); release(L.nbar);
         }
-        for (auto &g : h->graphs)
-            if (g.second.exec) hipGraphExecDestroy(g.second.exec);
-        for (auto &g : h->frame_graphs)
-            if (g.second.exec) hipGraphExecDestroy(g.second.exec);
+        for (auto &g : h->graphs) release_graph(g.second);
+        for (auto &g : h->frame_graphs) release_graph(g.second);
         release(h->batch_dev);
         if (h->batch_stage) hipHostFree(h->batch_stage);
         if (h->pin) hipHostFree(h->pin);
