@@ -164,6 +164,29 @@ def test_batch_of_mixed_small_frames_and_fallback_aggregation(fm):
                         assert np.array_equal(g[k], ones[i][k]), (variant, wls[i]["name"], k)
 
 
+def test_batch_of_frames_with_many_labels(fm):
+    """Frames whose levels take three and four packed label registers (four
+    families of 96 and of 120 labels) in the batch's persistent aggregation:
+    each frame equals its run alone."""
+    wls = []
+    for name, count in (("config3_small", 96), ("config3_small", 120)):
+        wl = copy.deepcopy(scenegen.make_workload(name))
+        for f in wl["families"]:
+            f["count"] = count
+        wl["params"]["window_labels"] = count
+        wls.append(wl)
+    ones = []
+    for wl in wls:
+        with fm.Handle(fm.config_from_params(wl["params"])) as h1:
+            ones.append(h1.run_frame(wl))
+    with fm.Handle(fm.config_from_params(wls[0]["params"])) as h:
+        got = h.run_batch(wls)
+    for i, g in enumerate(got):
+        for k in ("depth", "normal", "conf"):
+            assert np.array_equal(g[k], ones[i][k]), (wls[i]["name"], k)
+        assert np.mean(ones[i]["depth"] > 0) > 0.5
+
+
 def test_batch_errors(fm, frames):
     wl = frames[scenegen.CONFIG4_SEEDS[0]]
     with fm.Handle(fm.config_from_params(wl["params"])) as h:

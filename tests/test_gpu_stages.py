@@ -289,6 +289,8 @@ def test_sgm_path_gradient_bit_exact(orc, hd, monkeypatch, kernel, name, level):
     ((37, 53), [24, 16, 32], [40, 16, 64], 8),      # even windows, 72 labels
     ((37, 53), [23, 16, 9], [40, 16, 12], 8),       # odd windows (one-label kernel either way)
     ((21, 30), [200, 130], [260, 130], 8),          # 330 labels: three packed registers, ragged
+    ((17, 23), [96, 96, 96, 96], [192, 96, 128, 160], 8),   # 384 labels in four families
+    ((13, 19), [256, 200], [300, 200], 8),          # 456 labels: four packed registers
     ((19, 26), [128], [256], 4),                    # exactly 128 labels, four paths
     ((1, 41), [16, 8], [30, 8], 8),                 # one-row image
     ((33, 1), [16], [16], 8),                       # one-column image
