@@ -330,7 +330,7 @@ constexpr int PK_LW = (kMaxLabels + 2 * PK_G2 * kMaxFam) / 2 + 1;   // 32-bit wo
 template <int KP, int NF, bool WIN, bool SN, bool PG>
 __device__ __forceinline__ void sgm_pk_path(const SgmArgs a, const int path, const int *s_lut,
                                             const double *pdelta, uint32_t *buf0, uint32_t *buf1) {
-    constexpr int PF = KP >= 3 ? 8 : 16;   // steps per block (ring depth): fewer registers for many labels
+    constexpr int PF = KP >= 2 ? 8 : 16;   // steps per block (ring depth): fewer registers for many labels
     constexpr int G2 = PK_G2;
     constexpr int LW = PK_LW;
     const int lane = threadIdx.x & 63;
