@@ -7,9 +7,10 @@
 // occlusion-robust minimum, and the cost written to the label-innermost
 // uint8 volume S[y][x][label].
 //
-// Tile 64 x 32 pixels, 256 threads = 4 waves; thread (tx, ty) owns column
-// tx and rows 8ty..8ty+7, so every LDS row read serves up to eight census
-// windows.  The label range of a block is the union of its pixels' windows
+// Tile 64 x 4*RPT pixels, 256 threads = 4 waves; thread (tx, ty) owns
+// column tx and RPT consecutive rows (RPT 8 or 4, the caller's choice per
+// level), so every LDS row read serves up to RPT census windows.  The label
+// range of a block is the union of its pixels' windows
 // (dynamic cost volume); pixels whose window misses a label skip the store.
 // Costs leave in 4-byte words per pixel (label-innermost rows are
 // contiguous), so the L2 sees whole-word writes rather than single bytes.
