@@ -155,6 +155,25 @@ def test_frame_graph_replay_equals_launches(fm, monkeypatch):
     assert np.array_equal(runs["1"][0]["depth"], runs["1"][1]["depth"])
 
 
+@pytest.mark.parametrize("name", ["config2_small", "config3_small"])
+def test_frame_same_at_every_sweep_tile_height(fm, monkeypatch, name):
+    """The runtime's per-level sweep tile height (16-row tiles for several
+    plane families or small levels, 32-row otherwise) changes no result:
+    the maps equal those with 32-row and with 16-row tiles at every level."""
+    wl = scenegen.make_workload(name)
+    runs = {}
+    for rows in ("", "8", "4"):
+        if rows:
+            monkeypatch.setenv("FASSMVS_SWEEP_ROWS", rows)
+        else:
+            monkeypatch.delenv("FASSMVS_SWEEP_ROWS", raising=False)
+        with fm.Handle(fm.config_from_params(wl["params"])) as h:
+            runs[rows] = h.run_frame(wl)
+    for rows in ("8", "4"):
+        for k in ("depth", "normal", "conf"):
+            assert np.array_equal(runs[""][k], runs[rows][k]), (name, rows, k)
+
+
 def test_submit_with_one_depth_range_for_the_bundle(fm):
     """fassmvs_submit_frame_range: the bundle's depth range applied to every
     family without a distance range gives the maps of the same range given
