@@ -189,12 +189,13 @@ fassmvs_status fassmvs_poll(fassmvs_handle *h, uint64_t ticket, float *depth, fl
  * about equal work, each group on a stream of its own forked from and
  * joined back into the handle's stream.  A group runs level round by level
  * round (every frame's coarsest level first); in each round the sweeps of
- * its frames are one launch and their aggregations one persistent launch
- * per label-pair count over the paths of every frame and direction.  The
- * whole batch can be captured in a HIP graph once per batch shape and
- * replayed while the shape and the buffers stay; the sweep's tile height
- * and workgroup count, the number of groups and the graph are tuned once
- * per shape by timing the candidates (none of them changes a result).
+ * its frames are one launch per tile height and their aggregations one
+ * persistent launch per label-pair count over the paths of every frame and
+ * direction.  Each group's launches can be captured in a HIP graph once per
+ * batch shape and replayed while the shape and the buffers stay; the
+ * sweep's tile height and workgroup count, the number of groups (up to 16)
+ * and the graph are tuned once per shape by timing the candidates (none of
+ * them changes a result).
  * Each frame's maps are those fassmvs_submit_frame gives for the same
  * bundle.
  * --------------------------------------------------------------------- */
