@@ -252,5 +252,6 @@ int main() {
     if (!g_fail) served();
     if (!g_fail) planes();
     std::printf(g_fail ? "host check: FAILED\n" : "host check: ok\n");
+    std::fflush(stdout);
     return g_fail;
 }
