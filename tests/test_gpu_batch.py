@@ -76,7 +76,8 @@ def batched(fm, frames):
         try:
             with fm.Handle(fm.config_from_params(wls[0]["params"])) as h:
                 res[f"groups{G}_graph{graph}"] = h.run_batch(wls)
-                assert h.batch_tuning()["groups"] == G
+                # untuned: each frame level's own sweep tile height
+                assert h.batch_tuning()["groups"] == G and h.batch_tuning()["rows_per_thread"] == 0
         finally:
             for k in ("FASSMVS_BATCH_TUNE", "FASSMVS_BATCH_GROUPS", "FASSMVS_BATCH_GRAPH"):
                 del os.environ[k]
