@@ -188,6 +188,35 @@ def test_batch_of_frames_with_many_labels(fm):
         assert np.mean(ones[i]["depth"] > 0) > 0.5
 
 
+def test_batch_replay_with_new_images(fm, monkeypatch):
+    """A batch replayed from its captured group graphs (untuned: graphs on,
+    two frame groups) reads the images of the current submission: the same
+    shapes with other images give the maps of those images run alone."""
+    monkeypatch.setenv("FASSMVS_BATCH_TUNE", "0")
+    monkeypatch.setenv("FASSMVS_BATCH_GROUPS", "2")
+    monkeypatch.delenv("FASSMVS_BATCH_GRAPH", raising=False)
+    base = [scenegen.make_workload(n) for n in ("config2_small", "config2_ragged", "config3_small")]
+
+    def variant(wl, k):
+        w2 = copy.deepcopy(wl)
+        for im in [w2["ref"]] + w2["views"]:
+            im["img"] = np.ascontiguousarray(np.roll(im["img"], 3 * k, axis=1))
+        return w2
+
+    sets = [[variant(wl, k) for wl in base] for k in range(3)]
+    with fm.Handle(fm.config_from_params(base[0]["params"])) as h:
+        got = [h.run_batch(ws) for ws in sets]
+        t = h.batch_tuning()
+        assert t["graph"] and t["groups"] == 2
+    for k, ws in enumerate(sets):
+        for i, wl in enumerate(ws):
+            with fm.Handle(fm.config_from_params(wl["params"])) as h1:
+                one = h1.run_frame(wl)
+            for key in ("depth", "normal", "conf"):
+                assert np.array_equal(got[k][i][key], one[key]), (k, wl["name"], key)
+    assert not np.array_equal(got[0][0]["depth"], got[1][0]["depth"])
+
+
 def test_batch_errors(fm, frames):
     wl = frames[scenegen.CONFIG4_SEEDS[0]]
     with fm.Handle(fm.config_from_params(wl["params"])) as h:
