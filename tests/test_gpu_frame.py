@@ -4,6 +4,8 @@ Gates: plane labels identical on >= 99.9 % of pixels at every level, refined
 depth within 1e-3 relative where labels agree, warped intensities covered by
 the stage tests; normals / confidence within 1e-4 on the pixels whose depth
 stencil agrees (>= 99 % of each level)."""
+import copy
+
 import numpy as np
 import pytest
 
@@ -172,6 +174,28 @@ def test_frame_same_at_every_sweep_tile_height(fm, monkeypatch, name):
     for rows in ("8", "4"):
         for k in ("depth", "normal", "conf"):
             assert np.array_equal(runs[""][k], runs[rows][k]), (name, rows, k)
+
+
+def test_frame_graph_replay_with_new_images(fm, monkeypatch):
+    """A frame replayed from its captured graph reads the images of the
+    current submission: frames of one shape with other images give the maps
+    of the launch-by-launch path."""
+    base = scenegen.make_workload("config2_small")
+    wls = []
+    for k in range(3):
+        wl = copy.deepcopy(base)
+        for im in [wl["ref"]] + wl["views"]:
+            im["img"] = np.ascontiguousarray(np.roll(im["img"], 5 * k, axis=0))
+        wls.append(wl)
+    runs = {}
+    for graph in ("1", "0"):
+        monkeypatch.setenv("FASSMVS_FRAME_GRAPH", graph)
+        with fm.Handle(fm.config_from_params(base["params"], profile=0)) as h:
+            runs[graph] = [h.run_frame(wl) for wl in wls]
+    for i in range(len(wls)):
+        for k in ("depth", "normal", "conf"):
+            assert np.array_equal(runs["1"][i][k], runs["0"][i][k]), (i, k)
+    assert not np.array_equal(runs["1"][0]["depth"], runs["1"][1]["depth"])
 
 
 def test_submit_with_one_depth_range_for_the_bundle(fm):
